@@ -1,0 +1,28 @@
+"""Build oracle/liboracle.so from oracle/oracle.c with gcc (FP64, OpenMP, no fast-math).
+
+Test infrastructure only: the oracle is the checker, never part of the product path.
+"""
+from __future__ import annotations
+
+import subprocess
+import sys
+from pathlib import Path
+
+HERE = Path(__file__).resolve().parent
+
+
+def build(verbose: bool = False) -> Path:
+    src = HERE / "oracle.c"
+    out = HERE / "liboracle.so"
+    tmp = HERE / "liboracle.so.tmp"
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math",
+           "-Wall", "-Wextra", "-o", str(tmp), str(src), "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    tmp.replace(out)
+    return out
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,308 @@
+"""Python face of the FP64 CPU oracle (TEST INFRASTRUCTURE ONLY).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this module.  It loads ``oracle/liboracle.so`` (built
+from ``oracle/oracle.c`` by ``oracle/build.py``) and adds:
+
+  * the AQA / QAOA parameter schedules, written from Sec. III.B and Appendix A;
+  * a dense-matrix checker (Kronecker products + ``scipy.linalg.expm``) for
+    n <= 10, independent of the bit-loop code in ``oracle.c``;
+  * central finite differences with a Richardson pair for gradients.
+
+Nothing here imports the HIP library or the product package.
+
+Parity status of each function is documented in its docstring; every function
+below is pinned by a ``-m "not gpu"`` test (see tests/test_oracle_*.py).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+from pathlib import Path
+
+import numpy as np
+
+_HERE = Path(__file__).resolve().parent
+_LIB = None
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = _HERE / "liboracle.so"
+        if not path.exists():
+            from . import build as _b  # noqa: F401  (oracle/build.py)
+
+            _b.build()
+        L = ctypes.CDLL(str(path))
+        L.orc_energy.restype = ctypes.c_double
+        L.orc_energy.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _ip, _ip, _dp, ctypes.c_uint64]
+        L.orc_energies.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _ip, _ip, _dp, _dp]
+        L.orc_ground.argtypes = [ctypes.c_int, _dp, ctypes.c_double, _dp, _u64p, _u64p]
+        L.orc_init_plus.argtypes = [ctypes.c_int, _dp]
+        L.orc_cost_phase.argtypes = [ctypes.c_int, _dp, ctypes.c_double, _dp]
+        L.orc_rx.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp]
+        L.orc_mixer.argtypes = [ctypes.c_int, ctypes.c_double, _dp]
+        L.orc_qaoa.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp]
+        L.orc_observables.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_double,
+                                      _dp, _dp, _dp]
+        L.orc_spin_z.argtypes = [ctypes.c_int, _dp, _dp]
+        L.orc_grad_tangent.restype = ctypes.c_int
+        L.orc_grad_tangent.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, _dp, _dp, _dp]
+        L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
+        _LIB = L
+    return _LIB
+
+
+def _d(a):
+    return a.ctypes.data_as(_dp)
+
+
+def _i(a):
+    return a.ctypes.data_as(_ip)
+
+
+def num_threads() -> int:
+    return lib().orc_num_threads()
+
+
+def set_num_threads(t: int) -> None:
+    lib().orc_set_num_threads(int(t))
+
+
+# ----------------------------------------------------------------------------- energies
+def _inst(inst):
+    n = int(inst["n"])
+    h = np.ascontiguousarray(inst["h"], dtype=np.float64)
+    ei = np.ascontiguousarray(inst["ei"], dtype=np.int32)
+    ej = np.ascontiguousarray(inst["ej"], dtype=np.int32)
+    J = np.ascontiguousarray(inst["J"], dtype=np.float64)
+    return n, h, ei, ej, J
+
+
+def energy(inst, z: int) -> float:
+    """E(z) of Eq. HC with s_i = 2 b_i - 1 (|0> is the -1 eigenstate, Sec. III.A.3)."""
+    n, h, ei, ej, J = _inst(inst)
+    return lib().orc_energy(n, _d(h), len(J), _i(ei), _i(ej), _d(J), int(z))
+
+
+def energies(inst) -> np.ndarray:
+    """E(z) for all 2^n basis states (Eq. HC)."""
+    n, h, ei, ej, J = _inst(inst)
+    E = np.empty(1 << n, dtype=np.float64)
+    lib().orc_energies(n, _d(h), len(J), _i(ei), _i(ej), _d(J), _d(E))
+    return E
+
+
+def coeff_scale(inst) -> float:
+    """sum |h| + sum |J|: bound on |E(z)|, used to scale tolerances."""
+    return float(np.sum(np.abs(inst["h"])) + np.sum(np.abs(inst["J"])))
+
+
+def ground_tol(inst) -> float:
+    """Energies within this distance of the minimum count as ground states.
+    Integer-valued instances compare exactly (tolerance 0)."""
+    vals = np.concatenate([np.asarray(inst["h"]), np.asarray(inst["J"])])
+    if np.all(vals == np.round(vals)):
+        return 0.0
+    return 1e-9 * max(1.0, coeff_scale(inst))
+
+
+def ground(inst, E=None):
+    """Brute-force ground state: (E_min, degeneracy, smallest argmin)."""
+    n = int(inst["n"])
+    if E is None:
+        E = energies(inst)
+    emin = ctypes.c_double()
+    deg = ctypes.c_uint64()
+    am = ctypes.c_uint64()
+    lib().orc_ground(n, _d(E), ground_tol(inst), ctypes.byref(emin), ctypes.byref(deg), ctypes.byref(am))
+    return emin.value, int(deg.value), int(am.value)
+
+
+# ----------------------------------------------------------------------------- states
+def _c2i(psi: np.ndarray) -> np.ndarray:
+    """complex128[N] -> float64[2N] interleaved view/copy."""
+    return np.ascontiguousarray(psi, dtype=np.complex128).view(np.float64)
+
+
+def plus_state(n: int) -> np.ndarray:
+    psi = np.empty(1 << n, dtype=np.complex128)
+    lib().orc_init_plus(n, _d(psi.view(np.float64)))
+    return psi
+
+
+def cost_phase(inst, psi: np.ndarray, gamma: float, E=None) -> np.ndarray:
+    """exp(-i gamma H_C) psi (returns a new array)."""
+    if E is None:
+        E = energies(inst)
+    out = np.array(psi, dtype=np.complex128, copy=True)
+    lib().orc_cost_phase(int(inst["n"]), _d(E), float(gamma), _d(out.view(np.float64)))
+    return out
+
+
+def rx(n: int, psi: np.ndarray, q: int, beta: float) -> np.ndarray:
+    """exp(-i beta sigma^x_q) psi (Eq. twocomponentupdates)."""
+    out = np.array(psi, dtype=np.complex128, copy=True)
+    lib().orc_rx(n, int(q), float(beta), _d(out.view(np.float64)))
+    return out
+
+
+def mixer(n: int, psi: np.ndarray, beta: float) -> np.ndarray:
+    """exp(-i beta H_D) psi, H_D = sum_i sigma^x_i."""
+    out = np.array(psi, dtype=np.complex128, copy=True)
+    lib().orc_mixer(n, float(beta), _d(out.view(np.float64)))
+    return out
+
+
+def qaoa_state(inst, gamma, beta, psi0=None, E=None) -> np.ndarray:
+    """Eq. QAOA_state: prod_k exp(-i beta_k H_D) exp(-i gamma_k H_C) applied to
+    |+>^n (or to psi0 when given)."""
+    n = int(inst["n"])
+    gamma = np.ascontiguousarray(np.atleast_1d(gamma), dtype=np.float64)
+    beta = np.ascontiguousarray(np.atleast_1d(beta), dtype=np.float64)
+    assert len(gamma) == len(beta)
+    if E is None:
+        E = energies(inst)
+    if psi0 is None:
+        psi = np.empty(1 << n, dtype=np.complex128)
+        from_plus = 1
+    else:
+        psi = np.array(psi0, dtype=np.complex128, copy=True)
+        from_plus = 0
+    lib().orc_qaoa(n, _d(E), len(gamma), _d(gamma), _d(beta), from_plus, _d(psi.view(np.float64)))
+    return psi
+
+
+def observables(inst, psi, E=None, gs=None):
+    """(norm, <H_C>, ground-state probability) of psi (Sec. III.B.1)."""
+    n = int(inst["n"])
+    if E is None:
+        E = energies(inst)
+    if gs is None:
+        gs = ground(inst, E)
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    norm = ctypes.c_double()
+    en = ctypes.c_double()
+    pgs = ctypes.c_double()
+    lib().orc_observables(n, _d(E), _d(psi.view(np.float64)), gs[0], ground_tol(inst),
+                          ctypes.byref(norm), ctypes.byref(en), ctypes.byref(pgs))
+    return norm.value, en.value, pgs.value
+
+
+def spin_z(n: int, psi) -> np.ndarray:
+    """<sigma^z_i> for every qubit (spin expectations of Sec. III.B.2)."""
+    psi = np.ascontiguousarray(psi, dtype=np.complex128)
+    out = np.empty(n, dtype=np.float64)
+    lib().orc_spin_z(n, _d(psi.view(np.float64)), _d(out))
+    return out
+
+
+def grad_tangent(inst, gamma, beta, E=None):
+    """(f, df/dgamma, df/dbeta) for f = <beta,gamma|H_C|beta,gamma> by forward-mode
+    tangents (one extra state vector per parameter)."""
+    n = int(inst["n"])
+    gamma = np.ascontiguousarray(np.atleast_1d(gamma), dtype=np.float64)
+    beta = np.ascontiguousarray(np.atleast_1d(beta), dtype=np.float64)
+    p = len(gamma)
+    if E is None:
+        E = energies(inst)
+    dg = np.empty(p)
+    db = np.empty(p)
+    f = ctypes.c_double()
+    rc = lib().orc_grad_tangent(n, _d(E), p, _d(gamma), _d(beta), ctypes.byref(f), _d(dg), _d(db))
+    if rc != 0:
+        raise MemoryError("oracle gradient: allocation failed")
+    return f.value, dg, db
+
+
+def energy_of(inst, gamma, beta, E=None) -> float:
+    if E is None:
+        E = energies(inst)
+    psi = qaoa_state(inst, gamma, beta, E=E)
+    return observables(inst, psi, E=E, gs=(0.0, 0, 0))[1]
+
+
+def grad_fd(inst, gamma, beta, h=1e-4, E=None):
+    """Central finite differences with the Richardson pair (h, h/2):
+    g = (4 D(h/2) - D(h)) / 3, truncation O(h^4)."""
+    if E is None:
+        E = energies(inst)
+    gamma = np.array(np.atleast_1d(gamma), dtype=np.float64)
+    beta = np.array(np.atleast_1d(beta), dtype=np.float64)
+    p = len(gamma)
+
+    def central(vec_is_gamma, k, step):
+        g1, b1 = gamma.copy(), beta.copy()
+        g2, b2 = gamma.copy(), beta.copy()
+        if vec_is_gamma:
+            g1[k] += step
+            g2[k] -= step
+        else:
+            b1[k] += step
+            b2[k] -= step
+        return (energy_of(inst, g1, b1, E) - energy_of(inst, g2, b2, E)) / (2 * step)
+
+    dg = np.empty(p)
+    db = np.empty(p)
+    for k in range(p):
+        dg[k] = (4 * central(True, k, h / 2) - central(True, k, h)) / 3
+        db[k] = (4 * central(False, k, h / 2) - central(False, k, h)) / 3
+    return dg, db
+
+
+# ----------------------------------------------------------------------------- schedules
+def aqa_linear_schedule(steps: int, tau: float, paper_sign: bool = True):
+    """Coarse first-order annealing steps with A(s) = 1 - s, B(s) = s (a linear
+    stand-in for the DW_2000Q_6 schedule of Fig. 4, whose data is not available).
+
+    Step k = 1..steps applies exp(-i tau B(s_k) H_C) then exp(+i tau A(s_k) H_D)
+    with s_k = k/steps: the annealing Hamiltonian H(s) = A(s) H_I + B(s) H_C with
+    H_I = -H_D (Eq. HI, Eq. Hofs).  In QAOA variables that is gamma_k = tau s_k and
+    beta_k = -tau (1 - s_k).  ``paper_sign=False`` returns beta_k = +tau (1 - s_k),
+    i.e. evolution under +H_D, which anneals toward the maximum of H_C.
+    """
+    s = np.arange(1, steps + 1, dtype=np.float64) / steps
+    gamma = tau * s
+    beta = (-1.0 if paper_sign else 1.0) * tau * (1.0 - s)
+    return gamma, beta
+
+
+def second_order_schedule(p: int, tau: float, A=None, B=None):
+    """Second-order Suzuki-Trotter parameters (Eqs. beta_k-gamma_k, Appendix A).
+
+    Grid s_k = (k-1)/(p-1), k = 1..p (Sec. III.B.1); for AQA with n steps the same
+    grid arises from s_k = k/n, k = 0..n with p = n + 1 (Sec. III.B.2).
+      beta_k  = -tau (A(s_{k+1}) + A(s_k)) / 2,  k = 1..p-1
+      beta_p  = -tau A(s_p) / 2
+      gamma_k =  tau B(s_k),                       k = 1..p
+    A, B: callables of s or arrays of length p sampled on the grid; default to
+    the linear stand-in A = 1 - s, B = s.  p = 1 has no grid (0/0) and is rejected.
+    """
+    if p < 2:
+        raise ValueError("second-order schedule needs p >= 2")
+    s = np.arange(p, dtype=np.float64) / (p - 1)
+    a = _sample(A, s, lambda x: 1.0 - x)
+    b = _sample(B, s, lambda x: x)
+    beta = np.empty(p)
+    beta[:-1] = -tau * (a[1:] + a[:-1]) / 2.0
+    beta[-1] = -tau * a[-1] / 2.0
+    gamma = tau * b
+    return gamma, beta
+
+
+def _sample(f, s, default):
+    if f is None:
+        return default(s)
+    if callable(f):
+        return np.array([f(x) for x in s], dtype=np.float64)
+    arr = np.asarray(f, dtype=np.float64)
+    if arr.shape != s.shape:
+        raise ValueError("schedule array must have one value per grid point")
+    return arr
