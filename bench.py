@@ -1,0 +1,180 @@
+"""Benchmark: QAOA layers on one MI355X through the C ABI.
+
+Workload (the one the headline metric is quoted on): p = 4 QAOA layers at
+n = 32 qubits, complex128 amplitudes (64 GiB state), on a random Ising instance
+G(32, 64) with integer J in [-2, 2] and h in {-1, 0, 1} (seeded), followed by
+<H_C> and the ground-state probability.  One step = sv_qaoa_forward(p = 4) +
+sv_expect.  value = amplitude updates per second = p * 2^n * (n + 1) / t_step
+(n butterflies and one phase per amplitude per layer).
+
+Also reported (outside the timed steps): roofline of the dominant kernel
+(tile pass) from per-launch HIP events on the launch stream, the complex64
+rate, the adjoint gradient time against (2p + 1) forward evaluations, and the
+FP64 CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+ROOT = Path(__file__).resolve().parent
+if str(ROOT) not in sys.path:
+    sys.path.insert(0, str(ROOT))
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=32)
+    ap.add_argument("--p", type=int, default=4)
+    ap.add_argument("--dtype", default="c128")
+    ap.add_argument("--no-extras", action="store_true", help="skip gradient / c64 / CPU-baseline legs")
+    ap.add_argument("--cpu-sample-n", type=int, default=24)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2104_03293_amd import inputs as I
+    from paper_2104_03293_amd import sv
+
+    torch.cuda.set_device(0)
+    n, p = args.n, args.p
+    inst = I.config4_instance(n) if n >= 33 else I.degree4_int2(n, 4 + n)
+    H = sv.Ising.from_instance(inst)
+    gam, bet = I.linear_ramp_params(p)
+    log(f"[bench] n={n} p={p} dtype={args.dtype} ground...")
+    emin, deg, _ = sv.ground(H)
+    log(f"[bench] ground E_min={emin} degeneracy={deg}")
+    s = sv.State(n, args.dtype)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        sv.qaoa_forward(s, H, gam, bet)
+        return sv.expect(s, H)
+
+    for i in range(args.warmup):
+        step()
+        log(f"[bench] warmup {i + 1}/{args.warmup}")
+    torch.cuda.synchronize()
+    sv.profile_enable(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        out = step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = sv.profile_report()
+    sv.profile_enable(False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    updates = p * (1 << n) * (n + 1)
+    value = updates / (ms * 1e-3)
+    log(f"[bench] {ms:.3f} ms/step  {value:.4e} amp-updates/s  <H>={out[0]:.6f} P_gs={out[1]:.3e} norm={out[2]:.12f}")
+
+    # roofline of the tile-pass kernel (the only kernel with non-trivial time)
+    kind = f"pass_{args.dtype}_nv1"
+    k = prof.get(kind, {"launches": 0, "ms": 0.0, "bytes": 0.0})
+    avg_ms = k["ms"] / max(1, k["launches"])
+    avg_bytes = k["bytes"] / max(1, k["launches"])
+    achieved = avg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    roof = {"bound": "hbm", "kernel": f"k_pass<{args.dtype}>", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "launches_per_step": k["launches"] / args.steps, "avg_launch_ms": round(avg_ms, 4),
+            "algorithmic_bytes_per_launch": avg_bytes}
+
+    extras = {}
+    if not args.no_extras:
+        # adjoint gradient vs finite differences (2p + 1 forward evaluations)
+        lam = sv.State(n, args.dtype)
+        sv.grad(s, lam, H, gam, bet)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            e, dg, db = sv.grad(s, lam, H, gam, bet)
+        torch.cuda.synchronize()
+        t_grad = (time.perf_counter() - t0) / reps * 1e3
+        t_fd = (2 * p + 1) * ms
+        extras["grad"] = {"ms": round(t_grad, 3), "forward_ms": round(ms, 3), "fd_forward_diff_ms": round(t_fd, 3),
+                          "speedup_vs_fd": round(t_fd / t_grad, 3), "target": round((2 * p + 1) / 3, 3),
+                          "max_abs_grad": float(max(np.max(np.abs(dg)), np.max(np.abs(db))))}
+        log(f"[bench] grad {t_grad:.2f} ms vs FD {t_fd:.2f} ms")
+        del lam
+        # complex64 storage, same instance
+        s64 = sv.State(n, "c64")
+        sv.qaoa_forward(s64, H, gam, bet)
+        sv.expect(s64, H)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            sv.qaoa_forward(s64, H, gam, bet)
+            o64 = sv.expect(s64, H)
+        torch.cuda.synchronize()
+        ms64 = (time.perf_counter() - t0) * 1e3 / args.steps
+        extras["c64"] = {"ms_per_step": round(ms64, 3), "amp_updates_per_s": updates / (ms64 * 1e-3),
+                         "energy_diff_vs_c128": abs(o64[0] - out[0])}
+        log(f"[bench] c64 {ms64:.3f} ms/step")
+        del s64
+
+    cpu = None
+    if not args.no_extras:
+        cpu = cpu_baseline(args.cpu_sample_n, p)
+
+    res = {
+        "metric": "amplitude-updates/s per QAOA layer at n=32 (HBM roofline of the layer kernel; grad vs FD)",
+        "value": value,
+        "unit": "amplitude-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.dtype == "c128" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"QAOA p={p} forward + <H_C>/P_gs, n={n} {args.dtype}, random Ising G(n,2n) "
+                               f"J in [-2,2], h in {{-1,0,1}}", "n": n, "p": p, "amp_dtype": args.dtype},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "extras": extras,
+    }
+    print(json.dumps(res), flush=True)
+
+
+def cpu_baseline(n: int, p: int):
+    """FP64 oracle on the host cores: QAOA forward + observables at a bounded size."""
+    import numpy as np
+
+    from oracle import oracle as orc
+    from paper_2104_03293_amd import inputs as I
+
+    inst = I.degree4_int2(n, 4 + n)
+    g, b = I.linear_ramp_params(p)
+    E = orc.energies(inst)
+    t0 = time.perf_counter()
+    psi = orc.qaoa_state(inst, g, b, E=E)
+    orc.observables(inst, psi, E=E, gs=(float(E.min()), 1, 0))
+    dt = time.perf_counter() - t0
+    updates = p * (1 << n) * (n + 1)
+    log(f"[bench] cpu oracle n={n} p={p}: {dt:.2f} s on {orc.num_threads()} threads")
+    return {"value": updates / dt, "unit": "amplitude-updates/s", "cores": orc.num_threads(), "kind": "oracle",
+            "sample": f"QAOA p={p} forward + observables at n={n} (FP64 C/OpenMP oracle), {dt:.2f} s"}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,1306 @@
+// Host side of libsv: argument checking, tile planning, pass programs and
+// launch sequencing behind the C ABI of include/sv.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <set>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/sv.h"
+#include "sv_internal.h"
+
+using namespace svk;
+
+// ============================================================================ errors
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+extern "C" const char* sv_last_error(void) { return g_err.c_str(); }
+
+extern "C" const char* sv_version(void) { return "libsv 0.1.0 (gfx950)"; }
+
+#define HIPCHECK(expr)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(SV_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+// ============================================================================ knobs
+namespace {
+std::mutex g_knob_mu;
+std::map<std::string, int> g_knobs = {
+    {"fuse", 1},      // 1: snake-ordered fused passes; 0: one op per pass
+    {"cmin64", 4},    // minimum carrier bits (contiguous run 2^c amplitudes) for complex64
+    {"cmin128", 3},   // ... for complex128
+};
+int knob(const char* k) {
+    std::lock_guard<std::mutex> g(g_knob_mu);
+    return g_knobs[k];
+}
+}  // namespace
+
+extern "C" int sv_tune_set(const char* name, int value) {
+    if (!name) return fail(SV_ERR_ARG, "sv_tune_set: name is NULL");
+    std::lock_guard<std::mutex> g(g_knob_mu);
+    auto it = g_knobs.find(name);
+    if (it == g_knobs.end()) return fail(SV_ERR_ARG, "sv_tune_set: unknown knob '%s'", name);
+    if (std::string(name) == "fuse" && (value < 0 || value > 1)) return fail(SV_ERR_ARG, "fuse must be 0 or 1");
+    if ((std::string(name) == "cmin64" || std::string(name) == "cmin128") && (value < 0 || value > 8))
+        return fail(SV_ERR_ARG, "%s must be in [0, 8]", name);
+    it->second = value;
+    return SV_OK;
+}
+
+extern "C" int sv_tune_get(const char* name, int* value) {
+    if (!name || !value) return fail(SV_ERR_ARG, "sv_tune_get: NULL argument");
+    std::lock_guard<std::mutex> g(g_knob_mu);
+    auto it = g_knobs.find(name);
+    if (it == g_knobs.end()) return fail(SV_ERR_ARG, "sv_tune_get: unknown knob '%s'", name);
+    *value = it->second;
+    return SV_OK;
+}
+
+// ============================================================================ profiling
+// Optional per-launch timing with HIP events recorded on the launch stream,
+// plus the algorithmic bytes of each pass (vectors read + vectors written).
+namespace {
+struct ProfRec {
+    hipEvent_t a, b;
+    std::string kind;
+    double bytes;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof;
+}  // namespace
+
+static void prof_clear_locked() {
+    for (auto& r : g_prof) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    g_prof.clear();
+}
+
+extern "C" int sv_profile_enable(int on) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    prof_clear_locked();
+    g_prof_on = on != 0;
+    return SV_OK;
+}
+
+extern "C" int sv_profile_report(char* buf, size_t len) {
+    if (!buf || len == 0) return fail(SV_ERR_ARG, "sv_profile_report: empty buffer");
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    std::map<std::string, std::tuple<long, double, double>> agg;  // launches, ms, bytes
+    for (auto& r : g_prof) {
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e != hipSuccess) return fail(SV_ERR_HIP, "profile: %s", hipGetErrorString(e));
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) return fail(SV_ERR_HIP, "profile: %s", hipGetErrorString(e));
+        auto& t = agg[r.kind];
+        std::get<0>(t) += 1;
+        std::get<1>(t) += ms;
+        std::get<2>(t) += r.bytes;
+    }
+    std::string js = "{";
+    bool first = true;
+    for (auto& kv : agg) {
+        char tmp[256];
+        snprintf(tmp, sizeof(tmp), "%s\"%s\":{\"launches\":%ld,\"ms\":%.6f,\"bytes\":%.1f}", first ? "" : ",",
+                 kv.first.c_str(), std::get<0>(kv.second), std::get<1>(kv.second), std::get<2>(kv.second));
+        js += tmp;
+        first = false;
+    }
+    js += "}";
+    prof_clear_locked();
+    snprintf(buf, len, "%s", js.c_str());
+    return SV_OK;
+}
+
+static bool prof_begin(hipStream_t st, hipEvent_t* a) {
+    {
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        if (!g_prof_on) return false;
+    }
+    if (hipEventCreate(a) != hipSuccess) return false;
+    (void)hipEventRecord(*a, st);
+    return true;
+}
+
+static void prof_end(hipStream_t st, hipEvent_t a, const std::string& kind, double bytes) {
+    hipEvent_t b;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return;
+    }
+    (void)hipEventRecord(b, st);
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof.push_back(ProfRec{a, b, kind, bytes});
+}
+
+// ============================================================================ objects
+struct Work {
+    double* d_part = nullptr;
+    size_t part_cap = 0;  // doubles
+    double* d_res = nullptr;
+    double* h_res = nullptr;
+    size_t res_cap = 0;  // doubles
+};
+
+struct sv_state_s {
+    int n = 0;
+    sv_dtype dt = SV_C128;
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    bool owned = false;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    bool failed = false;
+    Work w;
+};
+
+struct GeoKey {
+    int T, R, c, lo, g, n;
+    bool operator<(const GeoKey& o) const {
+        return std::tie(T, R, c, lo, g, n) < std::tie(o.T, o.R, o.c, o.lo, o.g, o.n);
+    }
+};
+
+struct sv_ising_s {
+    int n = 0, m = 0;
+    std::vector<double> h, J;
+    std::vector<int32_t> ei, ej;
+    bool integer = true;
+    double scale = 0.0;
+    // device tables
+    double* d_h = nullptr;
+    int32_t* d_adj_ptr = nullptr;
+    int32_t* d_adj_nbr = nullptr;
+    double* d_adj_J = nullptr;
+    int32_t* d_ei = nullptr;
+    int32_t* d_ej = nullptr;
+    double* d_J = nullptr;
+    // ground cache
+    bool has_ground = false;
+    double emin = 0.0;
+    uint64_t deg = 0, argmin = 0;
+    std::map<GeoKey, GeoBuf*> geos;
+    std::mutex mu;
+};
+
+static size_t elem_size(sv_dtype d) { return d == SV_C128 ? 16 : 8; }
+static int max_n(sv_dtype d) { return d == SV_C128 ? 33 : 34; }
+static bool dtype_ok(int d) { return d == SV_C64 || d == SV_C128; }
+
+// ============================================================================ geometry
+// One tile geometry: carriers [0, c), group bits [lo, lo + g), phantom bits >= n.
+struct Geometry {
+    int T, R, c, lo, g, n;
+    uint32_t phantom;
+    uint64_t ntiles;
+    std::vector<std::vector<int>> blocks;  // register bit blocks per layout
+    std::vector<uint32_t> act_fwd, act_bwd;
+};
+
+static uint32_t swizzle(uint32_t u, int G) {
+    uint32_t x = u >> G, f = 0;
+    for (int i = 0; i < 6; i++) {
+        f ^= x;
+        x >>= G;
+    }
+    return u ^ (f & ((1u << G) - 1u));
+}
+
+static int swz_bits(sv_dtype d) { return d == SV_C128 ? 3 : 4; }
+
+// Register-bit blocks for a geometry: the first layout holds the top R tile
+// bits so that lanes run over tile bits 0..5 (coalesced loads); the low block
+// [0, R) comes second; the remaining active bits are covered from the top with
+// blocks starting at or above the swizzle width, so the last layout again has
+// the carriers as the lowest lane bits (coalesced stores).
+static Geometry make_geometry(int n, int T, int R, int c, int lo, int g, int G) {
+    Geometry geo{};
+    geo.T = T;
+    geo.R = R;
+    geo.c = c;
+    geo.lo = lo;
+    geo.g = g;
+    geo.n = n;
+    geo.phantom = 0;
+    for (int l = 0; l < T; l++)
+        if (l >= n) geo.phantom |= 1u << l;
+    geo.ntiles = n > T ? (1ull << (n - T)) : 1ull;
+    const bool groupA = (g == 0);
+    uint32_t active = 0;
+    if (groupA) {
+        for (int l = 0; l < std::min(n, T); l++) active |= 1u << l;
+    } else {
+        for (int l = c; l < T; l++) active |= 1u << l;
+    }
+    std::vector<std::pair<int, int>> blk;  // [a, a + R)
+    blk.push_back({T - R, T});
+    if (groupA) {
+        blk.push_back({0, R});
+        int hi = T - R;
+        while (hi > R) {
+            int a = std::max(hi - R, G);
+            blk.push_back({a, a + R});
+            hi = a;
+        }
+    } else {
+        int hi = T - R;
+        while (hi > c) {
+            int a = std::max(hi - R, c);
+            blk.push_back({a, a + R});
+            hi = a;
+        }
+    }
+    // keep blocks that touch active bits
+    std::vector<std::pair<int, int>> keep;
+    for (auto& b : blk) {
+        uint32_t m = 0;
+        for (int l = b.first; l < b.second; l++) m |= 1u << l;
+        if (m & active) keep.push_back(b);
+    }
+    if (keep.empty()) keep.push_back(blk[0]);
+    const int K = (int)keep.size();
+    for (auto& b : keep) {
+        std::vector<int> bits;
+        for (int l = b.first; l < b.second; l++) bits.push_back(l);
+        geo.blocks.push_back(bits);
+    }
+    geo.act_fwd.assign(K, 0);
+    geo.act_bwd.assign(K, 0);
+    uint32_t done = 0;
+    for (int j = 0; j < K; j++) {
+        for (int k = 0; k < R; k++) {
+            int l = geo.blocks[j][k];
+            if ((active >> l & 1u) && !(done >> l & 1u)) geo.act_fwd[j] |= 1u << k;
+        }
+        for (int l : geo.blocks[j]) done |= 1u << l;
+    }
+    done = 0;
+    for (int j = K - 1; j >= 0; j--) {
+        for (int k = 0; k < R; k++) {
+            int l = geo.blocks[j][k];
+            if ((active >> l & 1u) && !(done >> l & 1u)) geo.act_bwd[j] |= 1u << k;
+        }
+        for (int l : geo.blocks[j]) done |= 1u << l;
+    }
+    return geo;
+}
+
+// Tile groups covering all qubits: group A = tile bits 0..T-1 (contiguous),
+// then the bits above T split into near-equal groups of at most T - cmin bits,
+// each tile carrying 2^c contiguous amplitudes (c = T - g >= cmin).
+static std::vector<Geometry> plan_groups(int n, sv_dtype dt, int nv) {
+    const Shape sh = shape_for((int)dt, nv);
+    const int T = sh.T, R = sh.R, G = swz_bits(dt);
+    std::vector<Geometry> out;
+    if (n <= T) {
+        out.push_back(make_geometry(n, T, R, n, n, 0, G));
+        return out;
+    }
+    out.push_back(make_geometry(n, T, R, T, T, 0, G));
+    const int cmin = std::max(G, knob(dt == SV_C128 ? "cmin128" : "cmin64"));
+    const int rest = n - T, gmax = T - cmin;
+    const int ng = (rest + gmax - 1) / gmax;
+    int lo = T;
+    for (int i = 0; i < ng; i++) {
+        int g = rest / ng + (i < rest % ng ? 1 : 0);
+        out.push_back(make_geometry(n, T, R, T - g, lo, g, G));
+        lo += g;
+    }
+    return out;
+}
+
+static int global_bit(const Geometry& geo, int l) {
+    if (l >= geo.n) return -1;
+    if (l < geo.c) return l;
+    return geo.lo + (l - geo.c);
+}
+
+// Build the device table for a geometry and (optionally) an instance.
+static int build_geobuf(const Geometry& geo, const sv_ising_s* H, sv_dtype dt, GeoBuf** out) {
+    GeoBuf hb;
+    memset(&hb, 0, sizeof(hb));
+    const int T = geo.T, R = geo.R, G = swz_bits(dt);
+    std::vector<int> inv(64, -1);  // global bit -> tile bit
+    for (int l = 0; l < kMaxT; l++) {
+        hb.P[l] = (int8_t)(l < T ? global_bit(geo, l) : -1);
+        if (l < T && hb.P[l] >= 0) inv[hb.P[l]] = l;
+    }
+    auto gmap = [&](uint32_t u) -> uint64_t {
+        return (uint64_t)(u & ((1u << geo.c) - 1u)) | ((uint64_t)(u >> geo.c) << geo.lo);
+    };
+    const int K = (int)geo.blocks.size();
+    if (K > kMaxLayouts) return fail(SV_ERR_UNSUPPORTED, "internal: too many layouts (%d)", K);
+    for (int j = 0; j < K; j++) {
+        GeoLayout& L = hb.L[j];
+        const std::vector<int>& rb = geo.blocks[j];
+        uint32_t rmask = 0;
+        for (int k = 0; k < R; k++) {
+            L.rb[k] = (int8_t)rb[k];
+            rmask |= 1u << rb[k];
+        }
+        int nt = 0;
+        for (int l = 0; l < T; l++)
+            if (!(rmask >> l & 1u)) L.tb[nt++] = (int8_t)l;
+        L.ntb = nt;
+        L.act_fwd = (int32_t)geo.act_fwd[j];
+        L.act_bwd = (int32_t)geo.act_bwd[j];
+        for (int r = 0; r < (1 << R); r++) {
+            uint32_t u = 0;
+            for (int k = 0; k < R; k++)
+                if (r >> k & 1) u |= 1u << rb[k];
+            L.reg_u[r] = u;
+            L.reg_lds[r] = swizzle(u, G);
+            L.reg_goff[r] = (u & geo.phantom) ? 0 : gmap(u);
+        }
+        if (H) {
+            std::vector<int> slot_of(T, -1);
+            for (int k = 0; k < R; k++) slot_of[rb[k]] = k;
+            for (int e = 0; e < H->m; e++) {
+                const int la = inv[H->ei[e]], lb = inv[H->ej[e]];
+                if (la < 0 || lb < 0) continue;  // not an intra-tile coupling
+                const double Jv = H->J[e];
+                const int ka = slot_of[la], kb = slot_of[lb];
+                if (ka < 0 && kb < 0) {
+                    if (L.n_tt >= kMaxTT) return fail(SV_ERR_UNSUPPORTED, "internal: too many tile couplings");
+                    L.tt_a[L.n_tt] = (int8_t)la;
+                    L.tt_b[L.n_tt] = (int8_t)lb;
+                    L.tt_J[L.n_tt] = Jv;
+                    L.n_tt++;
+                } else if (ka >= 0 && kb >= 0) {
+                    for (int r = 0; r < (1 << R); r++) {
+                        const double sa = (r >> ka & 1) ? 1.0 : -1.0, sb = (r >> kb & 1) ? 1.0 : -1.0;
+                        L.Q[r] += Jv * sa * sb;
+                    }
+                } else {
+                    const int k = ka >= 0 ? ka : kb;
+                    const int lt = ka >= 0 ? lb : la;
+                    if (L.n_tr[k] >= kMaxTR) return fail(SV_ERR_UNSUPPORTED, "internal: too many couplings");
+                    L.tr_l[k][L.n_tr[k]] = (int8_t)lt;
+                    L.tr_J[k][L.n_tr[k]] = Jv;
+                    L.n_tr[k]++;
+                }
+            }
+        }
+    }
+    GeoBuf* d = nullptr;
+    HIPCHECK(hipMalloc(&d, sizeof(GeoBuf)));
+    hipError_t e = hipMemcpy(d, &hb, sizeof(GeoBuf), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return fail(SV_ERR_HIP, "hipMemcpy(geo) failed: %s", hipGetErrorString(e));
+    }
+    *out = d;
+    return SV_OK;
+}
+
+static std::mutex g_geo_mu;
+static std::map<GeoKey, GeoBuf*> g_plain_geos;  // instance-free tables (mixer-only passes)
+
+static int get_geobuf(const Geometry& geo, sv_ising_s* H, sv_dtype dt, GeoBuf** out) {
+    GeoKey key{geo.T, geo.R, geo.c, geo.lo, geo.g, geo.n};
+    if (H) {
+        std::lock_guard<std::mutex> g(H->mu);
+        auto it = H->geos.find(key);
+        if (it != H->geos.end()) {
+            *out = it->second;
+            return SV_OK;
+        }
+        int rc = build_geobuf(geo, H, dt, out);
+        if (rc) return rc;
+        H->geos[key] = *out;
+        return SV_OK;
+    }
+    std::lock_guard<std::mutex> g(g_geo_mu);
+    auto it = g_plain_geos.find(key);
+    if (it != g_plain_geos.end()) {
+        *out = it->second;
+        return SV_OK;
+    }
+    int rc = build_geobuf(geo, nullptr, dt, out);
+    if (rc) return rc;
+    g_plain_geos[key] = *out;
+    return SV_OK;
+}
+
+// ============================================================================ programs
+// Events of a circuit, in application order.
+enum EvKind { EV_INIT, EV_PHASE, EV_MIX, EV_REDUCE, EV_LAMINIT, EV_GGAMMA };
+struct Event {
+    EvKind kind;
+    int group = 0;      // EV_MIX
+    double angle = 0;   // EV_PHASE gamma / EV_MIX beta
+    int vec = 1;        // vectors touched (bit0 psi, bit1 lam)
+    int res = -1;       // result index (REDUCE: 3 consecutive; GGAMMA; MIX grad-beta)
+};
+
+struct Pass {
+    int group = 0;
+    int nv = 1;
+    bool has_mix = false;
+    bool init = false;
+    int load = 1, store = 1;
+    std::vector<Op> ops;
+    std::vector<int> slot_dst;                  // result index of each slot
+    std::vector<std::pair<int, double>> phase;  // (layout, gamma) per phase table
+};
+
+struct Program {
+    std::vector<Pass> passes;
+    int nres = 0;
+};
+
+static int point_rank(int flags) {
+    // position of a POINT part in the kernel's fixed execution order
+    if (flags & (PT_PHASE_PSI | PT_PHASE_LAM)) return 3;
+    if (flags & PT_GGAMMA) return 2;
+    if (flags & PT_LAM_INIT) return 1;
+    return 0;
+}
+
+// Partition events into passes (greedy): a pass keeps one tile group; POINT
+// work joins the open pass; a MIX on another group opens a new pass.
+static Program build_program(const std::vector<Event>& evs, int nres, bool fuse) {
+    Program prog;
+    prog.nres = nres;
+    Pass cur;
+    bool open = false;
+    auto close = [&]() {
+        if (open) prog.passes.push_back(cur);
+        cur = Pass();
+        open = false;
+    };
+    auto start = [&](int group) {
+        cur = Pass();
+        cur.group = group;
+        open = true;
+    };
+    for (const Event& e : evs) {
+        if (e.kind == EV_INIT) {
+            close();
+            start(0);
+            cur.init = true;
+            continue;
+        }
+        if (e.kind == EV_MIX) {
+            const int slots = e.res >= 0 ? 1 : 0;
+            bool can = open && (!cur.has_mix || (cur.group == e.group && fuse)) &&
+                       (int)cur.ops.size() < kMaxOps && (int)cur.slot_dst.size() + slots <= kMaxSlots;
+            if (!can) {
+                close();
+                start(e.group);
+            }
+            cur.group = e.group;  // POINT-only prefixes run in layout 0 of any group
+            Op op{};
+            op.kind = OP_MIX;
+            op.flags = (e.vec & 1 ? MIX_PSI : 0) | (e.vec & 2 ? MIX_LAM : 0);
+            op.slot = -1;
+            op.slot2 = -1;
+            op.qidx = -1;
+            if (e.res >= 0) {
+                op.flags |= MIX_GBETA;
+                op.slot = (int)cur.slot_dst.size();
+                cur.slot_dst.push_back(e.res);
+            }
+            op.a = std::cos(e.angle);
+            op.b = std::sin(e.angle);
+            cur.ops.push_back(op);
+            cur.has_mix = true;
+            continue;
+        }
+        int flag = 0;
+        if (e.kind == EV_PHASE) flag = (e.vec & 1 ? PT_PHASE_PSI : 0) | (e.vec & 2 ? PT_PHASE_LAM : 0);
+        if (e.kind == EV_REDUCE) flag = PT_REDUCE;
+        if (e.kind == EV_LAMINIT) flag = PT_LAM_INIT;
+        if (e.kind == EV_GGAMMA) flag = PT_GGAMMA;
+        if (!open || (!fuse && cur.has_mix)) {
+            close();
+            start(0);
+        }
+        const int slots = e.kind == EV_REDUCE ? 3 : (e.kind == EV_GGAMMA ? 1 : 0);
+        const bool is_phase = e.kind == EV_PHASE;
+        Op* last = cur.ops.empty() ? nullptr : &cur.ops.back();
+        bool merge = last && last->kind == OP_POINT && !(last->flags & flag);
+        if (merge) {
+            // the kernel runs POINT parts in a fixed order: merge only if that order
+            // agrees with the event order; a reduction reads only |psi|^2 and E, which
+            // a phase does not change, so it may move ahead of a phase.
+            const int mine = point_rank(flag);
+            const int lastmax = point_rank(last->flags);
+            merge = mine > lastmax ||
+                    (flag == PT_REDUCE && !(last->flags & (PT_LAM_INIT | PT_GGAMMA)));
+        }
+        const bool fits = (int)cur.slot_dst.size() + slots <= kMaxSlots &&
+                          (!is_phase || (int)cur.phase.size() < kMaxPhase) &&
+                          (merge || (int)cur.ops.size() < kMaxOps);
+        if (!fits) {
+            const int g = cur.has_mix ? cur.group : 0;
+            close();
+            start(g);
+            merge = false;
+        }
+        if (!merge) {
+            Op op{};
+            op.kind = OP_POINT;
+            op.slot = -1;
+            op.slot2 = -1;
+            op.qidx = -1;
+            cur.ops.push_back(op);
+        }
+        Op& op = cur.ops.back();
+        op.flags |= flag;
+        if (e.kind == EV_REDUCE) {
+            op.slot = (int)cur.slot_dst.size();
+            for (int q = 0; q < 3; q++) cur.slot_dst.push_back(e.res + q);
+        } else if (e.kind == EV_GGAMMA) {
+            op.slot2 = (int)cur.slot_dst.size();
+            cur.slot_dst.push_back(e.res);
+        } else if (e.kind == EV_PHASE) {
+            op.a = e.angle;
+            op.qidx = (int)cur.phase.size();
+            cur.phase.push_back({-1, e.angle});
+        }
+    }
+    close();
+    // vector liveness: load what holds data before a pass, store what holds data after
+    int live = 1;
+    for (Pass& p : prog.passes) {
+        if (p.init) live = 1;
+        p.load = p.init ? 4 : live;
+        bool touches_lam = (live & 2) != 0;
+        for (const Op& op : p.ops) {
+            if (op.kind == OP_POINT && (op.flags & PT_LAM_INIT)) live |= 2;
+            if (op.kind == OP_MIX && (op.flags & MIX_LAM)) touches_lam = true;
+            if (op.kind == OP_POINT && (op.flags & (PT_LAM_INIT | PT_GGAMMA | PT_PHASE_LAM))) touches_lam = true;
+        }
+        p.store = live;
+        p.nv = touches_lam ? 2 : 1;
+    }
+    return prog;
+}
+
+// Assign each phase table the layout its POINT op runs in: a MIX walks the
+// layouts from whichever end it is at to the other end.
+static void finalize_program(Program& prog, const std::vector<Geometry>* groups_by_nv) {
+    for (Pass& p : prog.passes) {
+        const int K = (int)groups_by_nv[p.nv][p.group].blocks.size();
+        int cur = 0;
+        for (Op& op : p.ops) {
+            if (op.kind == OP_MIX) {
+                if (K > 1) cur = (cur == 0) ? K - 1 : 0;
+            } else if (op.flags & (PT_PHASE_PSI | PT_PHASE_LAM)) {
+                p.phase[op.qidx].first = cur;
+            }
+        }
+    }
+}
+
+// ============================================================================ execution
+static int ensure_work(sv_state_s* s, size_t part_doubles, size_t res_doubles) {
+    Work& w = s->w;
+    if (part_doubles > w.part_cap) {
+        if (w.d_part) (void)hipFree(w.d_part);
+        w.d_part = nullptr;
+        w.part_cap = 0;
+        HIPCHECK(hipMalloc(&w.d_part, part_doubles * sizeof(double)));
+        w.part_cap = part_doubles;
+    }
+    if (res_doubles > w.res_cap) {
+        if (w.d_res) (void)hipFree(w.d_res);
+        if (w.h_res) (void)hipHostFree(w.h_res);
+        w.d_res = nullptr;
+        w.h_res = nullptr;
+        w.res_cap = 0;
+        HIPCHECK(hipMalloc(&w.d_res, res_doubles * sizeof(double)));
+        HIPCHECK(hipHostMalloc(&w.h_res, res_doubles * sizeof(double), hipHostMallocDefault));
+        w.res_cap = res_doubles;
+    }
+    return SV_OK;
+}
+
+static IsingDev ising_dev(const sv_ising_s* H) {
+    IsingDev d{};
+    if (!H) return d;
+    d.h = H->d_h;
+    d.adj_ptr = H->d_adj_ptr;
+    d.adj_nbr = H->d_adj_nbr;
+    d.adj_J = H->d_adj_J;
+    d.ei = H->d_ei;
+    d.ej = H->d_ej;
+    d.J = H->d_J;
+    d.n = H->n;
+    d.m = H->m;
+    return d;
+}
+
+static double ground_tol(const sv_ising_s* H) { return H->integer ? 0.0 : 1e-9 * std::max(1.0, H->scale); }
+
+static int run_ground(sv_ising_s* H, hipStream_t stream);
+
+// Run a program on state s (and lam for two-vector programs).
+struct Plan {
+    std::vector<Geometry> by_nv[3];  // [1]: one-vector tile shape, [2]: two-vector shape
+};
+
+static Plan make_plan(int n, sv_dtype dt) {
+    Plan pl;
+    pl.by_nv[1] = plan_groups(n, dt, 1);
+    pl.by_nv[2] = plan_groups(n, dt, 2);
+    return pl;
+}
+
+static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& prog, const Plan& plan,
+                       bool need_ground) {
+    finalize_program(prog, plan.by_nv);
+    if (s->failed) return fail(SV_ERR_HIP, "state is in a failed state after an earlier HIP error");
+    double emin = 0.0, etol = 0.0;
+    if (need_ground && H) {
+        int rc = run_ground(H, s->stream);
+        if (rc) return rc;
+        emin = H->emin;
+        etol = ground_tol(H);
+    }
+    size_t part_need = 1;
+    for (const Pass& p : prog.passes)
+        part_need = std::max(part_need, (size_t)plan.by_nv[p.nv][p.group].ntiles * std::max<size_t>(1, p.slot_dst.size()));
+    int rc = ensure_work(s, part_need, std::max(prog.nres, 1));
+    if (rc) return rc;
+    if (prog.nres > 0) {
+        hipError_t e = hipMemsetAsync(s->w.d_res, 0, prog.nres * sizeof(double), s->stream);
+        if (e != hipSuccess) {
+            s->failed = true;
+            return fail(SV_ERR_HIP, "hipMemsetAsync: %s", hipGetErrorString(e));
+        }
+    }
+    const double amp0 = std::pow(2.0, -0.5 * s->n);
+    for (const Pass& p : prog.passes) {
+        const Geometry& geo = plan.by_nv[p.nv][p.group];
+        if (p.nv == 2 && !lam) return fail(SV_ERR_ARG, "internal: two-vector pass without lam");
+        GeoBuf* gb = nullptr;
+        rc = get_geobuf(geo, H, s->dt, &gb);
+        if (rc) return rc;
+        PassArgs a;
+        memset(&a, 0, sizeof(a));
+        a.psi = s->ptr;
+        a.lam = lam ? lam->ptr : nullptr;
+        a.partials = s->w.d_part;
+        a.geo = gb;
+        a.is = ising_dev(H);
+        a.ntiles = geo.ntiles;
+        a.n = s->n;
+        a.c = geo.c;
+        a.lo = geo.lo;
+        a.g = geo.g;
+        a.phantom = geo.phantom;
+        a.nlayouts = (int)geo.blocks.size();
+        a.load = p.load;
+        a.store = p.store;
+        a.nslots = (int)p.slot_dst.size();
+        a.nops = (int)p.ops.size();
+        a.nphase = (int)p.phase.size();
+        for (int q = 0; q < a.nphase; q++) {
+            a.phase_layout[q] = p.phase[q].first;
+            a.phase_gamma[q] = p.phase[q].second;
+        }
+        a.emin = emin;
+        a.etol = etol;
+        a.amp0 = amp0;
+        for (int i = 0; i < a.nops; i++) a.ops[i] = p.ops[i];
+        hipEvent_t ev0;
+        const bool prof = prof_begin(s->stream, &ev0);
+        int e = launch_pass((int)s->dt, p.nv, a, s->stream);
+        if (prof) {
+            const int nrd = (p.load & 4) ? 0 : __builtin_popcount(p.load & 3);
+            const int nwr = __builtin_popcount(p.store & 3);
+            const std::string kind = std::string("pass_") + (s->dt == SV_C128 ? "c128" : "c64") + "_nv" +
+                                     std::to_string(p.nv);
+            prof_end(s->stream, ev0, kind, (double)(nrd + nwr) * (double)s->bytes);
+        }
+        if (e != 0) {
+            s->failed = true;
+            return fail(SV_ERR_HIP, "pass launch failed: %s", hipGetErrorString((hipError_t)e));
+        }
+        if (a.nslots > 0) {
+            e = launch_reduce_slots(s->w.d_part, geo.ntiles, a.nslots, p.slot_dst.data(), 1, s->w.d_res,
+                                    s->stream);
+            if (e != 0) {
+                s->failed = true;
+                return fail(SV_ERR_HIP, "reduce launch failed: %s", hipGetErrorString((hipError_t)e));
+            }
+        }
+    }
+    return SV_OK;
+}
+
+static int fetch_results(sv_state_s* s, int nres) {
+    if (nres <= 0) return SV_OK;
+    hipError_t e = hipMemcpyAsync(s->w.h_res, s->w.d_res, nres * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        s->failed = true;
+        return fail(SV_ERR_HIP, "result copy failed: %s", hipGetErrorString(e));
+    }
+    return SV_OK;
+}
+
+// ============================================================================ states
+extern "C" int sv_alloc(int n, sv_dtype dtype, void* stream, sv_state* out) {
+    if (!out) return fail(SV_ERR_ARG, "sv_alloc: out is NULL");
+    if (!dtype_ok(dtype)) return fail(SV_ERR_ARG, "sv_alloc: bad dtype %d", (int)dtype);
+    if (n < 1 || n > max_n(dtype)) return fail(SV_ERR_ARG, "sv_alloc: n=%d outside [1, %d]", n, max_n(dtype));
+    const size_t bytes = (size_t(1) << n) * elem_size(dtype);
+    size_t fr = 0, tot = 0;
+    hipError_t e = hipMemGetInfo(&fr, &tot);
+    if (e != hipSuccess) return fail(SV_ERR_HIP, "hipMemGetInfo: %s", hipGetErrorString(e));
+    if (bytes > fr) return fail(SV_ERR_OOM, "sv_alloc: need %zu bytes, %zu free", bytes, fr);
+    void* p = nullptr;
+    e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SV_ERR_OOM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    auto* s = new sv_state_s();
+    s->n = n;
+    s->dt = dtype;
+    s->ptr = p;
+    s->bytes = bytes;
+    s->owned = true;
+    s->stream = (hipStream_t)stream;
+    (void)hipGetDevice(&s->device);
+    *out = s;
+    return SV_OK;
+}
+
+extern "C" int sv_wrap(int n, sv_dtype dtype, void* ptr, size_t bytes, void* stream, sv_state* out) {
+    if (!out) return fail(SV_ERR_ARG, "sv_wrap: out is NULL");
+    if (!dtype_ok(dtype)) return fail(SV_ERR_ARG, "sv_wrap: bad dtype %d", (int)dtype);
+    if (n < 1 || n > max_n(dtype)) return fail(SV_ERR_ARG, "sv_wrap: n=%d outside [1, %d]", n, max_n(dtype));
+    if (!ptr) return fail(SV_ERR_ARG, "sv_wrap: NULL device pointer");
+    if ((uintptr_t)ptr % 16) return fail(SV_ERR_ARG, "sv_wrap: pointer not 16-byte aligned");
+    const size_t need = (size_t(1) << n) * elem_size(dtype);
+    if (bytes < need) return fail(SV_ERR_ARG, "sv_wrap: %zu bytes given, %zu needed", bytes, need);
+    auto* s = new sv_state_s();
+    s->n = n;
+    s->dt = dtype;
+    s->ptr = ptr;
+    s->bytes = need;
+    s->owned = false;
+    s->stream = (hipStream_t)stream;
+    (void)hipGetDevice(&s->device);
+    *out = s;
+    return SV_OK;
+}
+
+extern "C" int sv_free(sv_state s) {
+    if (!s) return SV_OK;
+    if (s->owned && s->ptr) (void)hipFree(s->ptr);
+    if (s->w.d_part) (void)hipFree(s->w.d_part);
+    if (s->w.d_res) (void)hipFree(s->w.d_res);
+    if (s->w.h_res) (void)hipHostFree(s->w.h_res);
+    delete s;
+    return SV_OK;
+}
+
+extern "C" int sv_set_stream(sv_state s, void* stream) {
+    if (!s) return fail(SV_ERR_ARG, "sv_set_stream: NULL state");
+    s->stream = (hipStream_t)stream;
+    return SV_OK;
+}
+
+extern "C" int sv_copy_to_host(sv_state s, void* host, size_t bytes) {
+    if (!s || !host) return fail(SV_ERR_ARG, "sv_copy_to_host: NULL argument");
+    if (bytes != s->bytes) return fail(SV_ERR_ARG, "sv_copy_to_host: %zu bytes, state has %zu", bytes, s->bytes);
+    if (s->failed) return fail(SV_ERR_HIP, "state is in a failed state");
+    hipError_t e = hipMemcpyAsync(host, s->ptr, bytes, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        s->failed = true;
+        return fail(SV_ERR_HIP, "copy to host: %s", hipGetErrorString(e));
+    }
+    return SV_OK;
+}
+
+extern "C" int sv_copy_from_host(sv_state s, const void* host, size_t bytes) {
+    if (!s || !host) return fail(SV_ERR_ARG, "sv_copy_from_host: NULL argument");
+    if (bytes != s->bytes) return fail(SV_ERR_ARG, "sv_copy_from_host: %zu bytes, state has %zu", bytes, s->bytes);
+    if (s->failed) return fail(SV_ERR_HIP, "state is in a failed state");
+    hipError_t e = hipMemcpyAsync(s->ptr, host, bytes, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) {
+        s->failed = true;
+        return fail(SV_ERR_HIP, "copy from host: %s", hipGetErrorString(e));
+    }
+    return SV_OK;
+}
+
+// ============================================================================ instances
+extern "C" int sv_ising_create(int n, const double* h, int m, const int32_t* ei, const int32_t* ej,
+                               const double* J, sv_ising* out) {
+    if (!out) return fail(SV_ERR_ARG, "sv_ising_create: out is NULL");
+    if (n < 1 || n > 34) return fail(SV_ERR_ARG, "sv_ising_create: n=%d outside [1, 34]", n);
+    if (m < 0) return fail(SV_ERR_ARG, "sv_ising_create: m=%d < 0", m);
+    if (!h) return fail(SV_ERR_ARG, "sv_ising_create: h is NULL");
+    if (m > 0 && (!ei || !ej || !J)) return fail(SV_ERR_ARG, "sv_ising_create: coupling arrays are NULL");
+    std::set<std::pair<int, int>> seen;
+    for (int i = 0; i < n; i++)
+        if (!std::isfinite(h[i])) return fail(SV_ERR_NUMERIC, "sv_ising_create: h[%d] is not finite", i);
+    for (int k = 0; k < m; k++) {
+        const int a = ei[k], b = ej[k];
+        if (a < 0 || a >= n || b < 0 || b >= n)
+            return fail(SV_ERR_ARG, "sv_ising_create: coupling %d has endpoint outside [0, %d)", k, n);
+        if (a == b) return fail(SV_ERR_ARG, "sv_ising_create: coupling %d is a self-coupling (%d, %d)", k, a, b);
+        if (!std::isfinite(J[k])) return fail(SV_ERR_NUMERIC, "sv_ising_create: J[%d] is not finite", k);
+        auto key = std::make_pair(std::min(a, b), std::max(a, b));
+        if (!seen.insert(key).second)
+            return fail(SV_ERR_ARG, "sv_ising_create: pair (%d, %d) listed twice", key.first, key.second);
+    }
+    auto* H = new sv_ising_s();
+    H->n = n;
+    H->m = m;
+    H->h.assign(h, h + n);
+    if (m > 0) {
+        H->ei.assign(ei, ei + m);
+        H->ej.assign(ej, ej + m);
+        H->J.assign(J, J + m);
+    }
+    for (double v : H->h) {
+        H->integer = H->integer && v == std::round(v);
+        H->scale += std::fabs(v);
+    }
+    for (double v : H->J) {
+        H->integer = H->integer && v == std::round(v);
+        H->scale += std::fabs(v);
+    }
+    // CSR adjacency over both endpoints
+    std::vector<int32_t> ptr(n + 1, 0), nbr(2 * m);
+    std::vector<double> aj(2 * m);
+    for (int k = 0; k < m; k++) {
+        ptr[H->ei[k] + 1]++;
+        ptr[H->ej[k] + 1]++;
+    }
+    for (int i = 0; i < n; i++) ptr[i + 1] += ptr[i];
+    std::vector<int32_t> fill(ptr.begin(), ptr.end() - 1);
+    for (int k = 0; k < m; k++) {
+        nbr[fill[H->ei[k]]] = H->ej[k];
+        aj[fill[H->ei[k]]++] = H->J[k];
+        nbr[fill[H->ej[k]]] = H->ei[k];
+        aj[fill[H->ej[k]]++] = H->J[k];
+    }
+    auto up = [&](void** dst, const void* src, size_t bytes) -> hipError_t {
+        hipError_t e = hipMalloc(dst, std::max<size_t>(bytes, 8));
+        if (e != hipSuccess) return e;
+        if (bytes) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+        return e;
+    };
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = up((void**)&H->d_h, H->h.data(), n * sizeof(double));
+    if (e == hipSuccess) e = up((void**)&H->d_adj_ptr, ptr.data(), (n + 1) * sizeof(int32_t));
+    if (e == hipSuccess) e = up((void**)&H->d_adj_nbr, nbr.data(), 2 * m * sizeof(int32_t));
+    if (e == hipSuccess) e = up((void**)&H->d_adj_J, aj.data(), 2 * m * sizeof(double));
+    if (e == hipSuccess) e = up((void**)&H->d_ei, H->ei.data(), m * sizeof(int32_t));
+    if (e == hipSuccess) e = up((void**)&H->d_ej, H->ej.data(), m * sizeof(int32_t));
+    if (e == hipSuccess) e = up((void**)&H->d_J, H->J.data(), m * sizeof(double));
+    if (e != hipSuccess) {
+        sv_ising_free(H);
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? SV_ERR_OOM : SV_ERR_HIP, "sv_ising_create: %s", hipGetErrorString(e));
+    }
+    *out = H;
+    return SV_OK;
+}
+
+extern "C" int sv_ising_free(sv_ising H) {
+    if (!H) return SV_OK;
+    for (void* p : {(void*)H->d_h, (void*)H->d_adj_ptr, (void*)H->d_adj_nbr, (void*)H->d_adj_J, (void*)H->d_ei,
+                    (void*)H->d_ej, (void*)H->d_J})
+        if (p) (void)hipFree(p);
+    for (auto& kv : H->geos) (void)hipFree(kv.second);
+    delete H;
+    return SV_OK;
+}
+
+// ============================================================================ ground
+static int run_ground(sv_ising_s* H, hipStream_t stream) {
+    {
+        std::lock_guard<std::mutex> g(H->mu);
+        if (H->has_ground) return SV_OK;
+    }
+    const sv_dtype dt = SV_C64;  // enumeration tiles use the complex64 tile shape
+    const Shape sh = shape_for((int)dt, 1);
+    std::vector<Geometry> groups = plan_groups(H->n, dt, 1);
+    const Geometry& geo = groups[0];
+    GeoBuf* gb = nullptr;
+    int rc = get_geobuf(geo, H, dt, &gb);
+    if (rc) return rc;
+    (void)sh;
+    double* d_e = nullptr;
+    uint64_t *d_c = nullptr, *d_a = nullptr;
+    double* d_out = nullptr;
+    const size_t nt = geo.ntiles;
+    HIPCHECK(hipMalloc(&d_e, nt * sizeof(double)));
+    HIPCHECK(hipMalloc(&d_c, nt * sizeof(uint64_t)));
+    HIPCHECK(hipMalloc(&d_a, nt * sizeof(uint64_t)));
+    HIPCHECK(hipMalloc(&d_out, 3 * sizeof(double)));
+    GroundArgs a;
+    memset(&a, 0, sizeof(a));
+    a.geo = gb;
+    a.is = ising_dev(H);
+    a.ntiles = geo.ntiles;
+    a.n = H->n;
+    a.c = geo.c;
+    a.lo = geo.lo;
+    a.g = geo.g;
+    a.phantom = geo.phantom;
+    a.part_e = d_e;
+    a.part_cnt = d_c;
+    a.part_arg = d_a;
+    a.mode = 0;
+    int e = launch_ground((int)dt, a, stream);
+    if (!e) e = launch_ground_finish(a, d_out, nullptr, nullptr, stream);
+    double emin = 0;
+    if (!e) e = (int)hipMemcpyAsync(&emin, d_out, sizeof(double), hipMemcpyDeviceToHost, stream);
+    if (!e) e = (int)hipStreamSynchronize(stream);
+    uint64_t cnt = 0, arg = 0;
+    if (!e) {
+        a.mode = 1;
+        a.emin = emin;
+        a.etol = ground_tol(H);
+        e = launch_ground((int)dt, a, stream);
+        if (!e) e = launch_ground_finish(a, nullptr, (uint64_t*)(d_out + 1), (uint64_t*)(d_out + 2), stream);
+        uint64_t tmp[2];
+        if (!e) e = (int)hipMemcpyAsync(tmp, d_out + 1, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost, stream);
+        if (!e) e = (int)hipStreamSynchronize(stream);
+        cnt = tmp[0];
+        arg = tmp[1];
+    }
+    (void)hipFree(d_e);
+    (void)hipFree(d_c);
+    (void)hipFree(d_a);
+    (void)hipFree(d_out);
+    if (e) return fail(SV_ERR_HIP, "ground enumeration failed: %s", hipGetErrorString((hipError_t)e));
+    std::lock_guard<std::mutex> g(H->mu);
+    H->emin = emin;
+    H->deg = cnt;
+    H->argmin = arg;
+    H->has_ground = true;
+    return SV_OK;
+}
+
+extern "C" int sv_ground(sv_ising H, double* e_min, uint64_t* degeneracy, uint64_t* argmin) {
+    if (!H) return fail(SV_ERR_ARG, "sv_ground: NULL instance");
+    int rc = run_ground(H, nullptr);
+    if (rc) return rc;
+    if (e_min) *e_min = H->emin;
+    if (degeneracy) *degeneracy = H->deg;
+    if (argmin) *argmin = H->argmin;
+    return SV_OK;
+}
+
+// ============================================================================ drivers
+static int check_pair(sv_state s, sv_ising H, const char* who) {
+    if (!s) return fail(SV_ERR_ARG, "%s: NULL state", who);
+    if (!H) return fail(SV_ERR_ARG, "%s: NULL instance", who);
+    if (s->n != H->n) return fail(SV_ERR_ARG, "%s: state has n=%d, instance n=%d", who, s->n, H->n);
+    return SV_OK;
+}
+
+static int check_angles(int p, const double* a, const double* b, const char* who) {
+    if (p < 1) return fail(SV_ERR_ARG, "%s: p=%d < 1", who, p);
+    if (!a || !b) return fail(SV_ERR_ARG, "%s: NULL angle array", who);
+    for (int k = 0; k < p; k++)
+        if (!std::isfinite(a[k]) || !std::isfinite(b[k]))
+            return fail(SV_ERR_NUMERIC, "%s: non-finite angle at layer %d", who, k + 1);
+    return SV_OK;
+}
+
+extern "C" int sv_init_plus(sv_state s) {
+    if (!s) return fail(SV_ERR_ARG, "sv_init_plus: NULL state");
+    Plan plan = make_plan(s->n, s->dt);
+    Program prog = build_program({Event{EV_INIT}}, 0, true);
+    return run_program(s, nullptr, nullptr, prog, plan, false);
+}
+
+extern "C" int sv_cost_phase(sv_state s, sv_ising H, double gamma) {
+    int rc = check_pair(s, H, "sv_cost_phase");
+    if (rc) return rc;
+    if (!std::isfinite(gamma)) return fail(SV_ERR_NUMERIC, "sv_cost_phase: gamma is not finite");
+    Plan plan = make_plan(s->n, s->dt);
+    Event e{EV_PHASE};
+    e.angle = gamma;
+    Program prog = build_program({e}, 0, true);
+    return run_program(s, nullptr, H, prog, plan, false);
+}
+
+static void push_mixer(std::vector<Event>& ev, int ngroups, double beta, bool reversed, int vec, int res) {
+    for (int i = 0; i < ngroups; i++) {
+        Event e{EV_MIX};
+        e.group = reversed ? ngroups - 1 - i : i;
+        e.angle = beta;
+        e.vec = vec;
+        e.res = res;
+        ev.push_back(e);
+    }
+}
+
+extern "C" int sv_mixer(sv_state s, double beta) {
+    if (!s) return fail(SV_ERR_ARG, "sv_mixer: NULL state");
+    if (!std::isfinite(beta)) return fail(SV_ERR_NUMERIC, "sv_mixer: beta is not finite");
+    Plan plan = make_plan(s->n, s->dt);
+    std::vector<Event> ev;
+    push_mixer(ev, (int)plan.by_nv[1].size(), beta, false, 1, -1);
+    Program prog = build_program(ev, 0, true);
+    return run_program(s, nullptr, nullptr, prog, plan, false);
+}
+
+// Forward circuit events: layer k applies the phase then the mixer groups in
+// snake order (odd layers ascending, even layers descending), so consecutive
+// layers meet on the same tile group and share a pass.
+static void forward_events(std::vector<Event>& ev, int ngroups, int p, const double* gamma, const double* beta,
+                           bool from_plus, int reduce_every_step_base) {
+    if (from_plus) ev.push_back(Event{EV_INIT});
+    for (int k = 0; k < p; k++) {
+        Event ph{EV_PHASE};
+        ph.angle = gamma[k];
+        ev.push_back(ph);
+        push_mixer(ev, ngroups, beta[k], (k % 2) == 1, 1, -1);
+        if (reduce_every_step_base >= 0) {
+            Event r{EV_REDUCE};
+            r.res = reduce_every_step_base + 3 * k;
+            ev.push_back(r);
+        }
+    }
+}
+
+extern "C" int sv_qaoa_forward(sv_state s, sv_ising H, int p, const double* gamma, const double* beta,
+                               int from_plus) {
+    int rc = check_pair(s, H, "sv_qaoa_forward");
+    if (rc) return rc;
+    rc = check_angles(p, gamma, beta, "sv_qaoa_forward");
+    if (rc) return rc;
+    Plan plan = make_plan(s->n, s->dt);
+    std::vector<Event> ev;
+    forward_events(ev, (int)plan.by_nv[1].size(), p, gamma, beta, from_plus != 0, -1);
+    Program prog = build_program(ev, 0, knob("fuse") != 0);
+    return run_program(s, nullptr, H, prog, plan, false);
+}
+
+extern "C" int sv_aqa_run(sv_state s, sv_ising H, int steps, const double* gamma, const double* beta,
+                          double* pgs_per_step, double* energy_per_step) {
+    int rc = check_pair(s, H, "sv_aqa_run");
+    if (rc) return rc;
+    rc = check_angles(steps, gamma, beta, "sv_aqa_run");
+    if (rc) return rc;
+    const bool want = pgs_per_step || energy_per_step;
+    Plan plan = make_plan(s->n, s->dt);
+    std::vector<Event> ev;
+    forward_events(ev, (int)plan.by_nv[1].size(), steps, gamma, beta, true, want ? 0 : -1);
+    Program prog = build_program(ev, want ? 3 * steps : 0, knob("fuse") != 0);
+    rc = run_program(s, nullptr, H, prog, plan, want);
+    if (rc || !want) return rc;
+    rc = fetch_results(s, 3 * steps);
+    if (rc) return rc;
+    for (int k = 0; k < steps; k++) {
+        if (pgs_per_step) pgs_per_step[k] = s->w.h_res[3 * k + 2];
+        if (energy_per_step) energy_per_step[k] = s->w.h_res[3 * k + 1];
+    }
+    return SV_OK;
+}
+
+extern "C" int sv_expect(sv_state s, sv_ising H, double* energy, double* p_gs, double* norm) {
+    int rc = check_pair(s, H, "sv_expect");
+    if (rc) return rc;
+    Plan plan = make_plan(s->n, s->dt);
+    Event r{EV_REDUCE};
+    r.res = 0;
+    Program prog = build_program({r}, 3, true);
+    prog.passes[0].store = 0;
+    rc = run_program(s, nullptr, H, prog, plan, true);
+    if (rc) return rc;
+    rc = fetch_results(s, 3);
+    if (rc) return rc;
+    if (norm) *norm = s->w.h_res[0];
+    if (energy) *energy = s->w.h_res[1];
+    if (p_gs) *p_gs = s->w.h_res[2];
+    return SV_OK;
+}
+
+// Reverse sweep of the adjoint method.  Result layout: [0..2] norm, energy,
+// pgs; [3 + k] = sum E Im(conj lam psi) for gamma_k; [3 + p + k] = pair sums
+// for beta_k.  df/dgamma_k = 2 * res[3+k], df/dbeta_k = 2 * res[3+p+k].
+extern "C" int sv_grad(sv_state psi, sv_state lam, sv_ising H, int p, const double* gamma, const double* beta,
+                       int psi_is_forward, double* energy, double* dgamma, double* dbeta) {
+    int rc = check_pair(psi, H, "sv_grad");
+    if (rc) return rc;
+    if (!lam) return fail(SV_ERR_ARG, "sv_grad: NULL lam state");
+    if (lam == psi) return fail(SV_ERR_ARG, "sv_grad: psi and lam must be different states");
+    if (lam->n != psi->n || lam->dt != psi->dt)
+        return fail(SV_ERR_ARG, "sv_grad: lam (n=%d, dtype=%d) does not match psi (n=%d, dtype=%d)", lam->n,
+                    (int)lam->dt, psi->n, (int)psi->dt);
+    if (!dgamma || !dbeta) return fail(SV_ERR_ARG, "sv_grad: NULL gradient output");
+    rc = check_angles(p, gamma, beta, "sv_grad");
+    if (rc) return rc;
+    if (lam->failed) return fail(SV_ERR_HIP, "lam state is in a failed state");
+    // both vectors share one tile geometry: plan with the two-vector shape
+    Plan plan = make_plan(psi->n, psi->dt);
+    const int G = (int)plan.by_nv[1].size();
+    std::vector<Event> ev;
+    if (!psi_is_forward) forward_events(ev, G, p, gamma, beta, true, -1);
+    Event r{EV_REDUCE};
+    r.res = 0;
+    ev.push_back(r);
+    ev.push_back(Event{EV_LAMINIT});
+    for (int k = p - 1; k >= 0; k--) {
+        // undo the mixer of layer k (groups in the reverse of their forward order)
+        push_mixer(ev, G, -beta[k], (k % 2) == 0, 3, 3 + p + k);
+        Event gg{EV_GGAMMA};
+        gg.res = 3 + k;
+        ev.push_back(gg);
+        if (k > 0) {
+            Event ph{EV_PHASE};
+            ph.angle = -gamma[k];
+            ph.vec = 3;
+            ev.push_back(ph);
+        }
+    }
+    Program prog = build_program(ev, 3 + 2 * p, knob("fuse") != 0);
+    // Trims.  In the pass where lam = E psi is formed, psi is mixed forward by
+    // one group and then undone by the same group: the loaded values are already
+    // that result, so psi is not written back.  The final pass writes nothing.
+    if (!psi_is_forward) {
+        for (Pass& ps : prog.passes) {
+            int fwd = -1, undo = -1, other = 0, laminit = -1;
+            for (int i = 0; i < (int)ps.ops.size(); i++) {
+                const Op& op = ps.ops[i];
+                if (op.kind == OP_POINT && (op.flags & PT_LAM_INIT)) laminit = i;
+                if (op.kind == OP_POINT && (op.flags & PT_PHASE_PSI)) other++;
+                if (op.kind == OP_MIX && (op.flags & MIX_PSI)) {
+                    if (laminit < 0) {
+                        if (fwd >= 0) other++;
+                        fwd = i;
+                    } else {
+                        if (undo >= 0) other++;
+                        undo = i;
+                    }
+                }
+            }
+            if (laminit >= 0 && fwd >= 0 && undo >= 0 && other == 0 && !ps.init &&
+                ps.ops[fwd].a == ps.ops[undo].a && ps.ops[fwd].b == -ps.ops[undo].b)
+                ps.store &= ~1;
+        }
+    }
+    prog.passes.back().store = 0;
+    rc = run_program(psi, lam, H, prog, plan, false);
+    if (rc) return rc;
+    rc = fetch_results(psi, 3 + 2 * p);
+    if (rc) return rc;
+    if (energy) *energy = psi->w.h_res[1];
+    for (int k = 0; k < p; k++) {
+        dgamma[k] = 2.0 * psi->w.h_res[3 + k];
+        dbeta[k] = 2.0 * psi->w.h_res[3 + p + k];
+    }
+    return SV_OK;
+}
+
+// ============================================================================ schedules
+extern "C" int sv_schedule_linear(int steps, double tau, int paper_sign, double* gamma, double* beta) {
+    if (steps < 1) return fail(SV_ERR_ARG, "sv_schedule_linear: steps=%d < 1", steps);
+    if (!gamma || !beta) return fail(SV_ERR_ARG, "sv_schedule_linear: NULL output");
+    if (!std::isfinite(tau)) return fail(SV_ERR_NUMERIC, "sv_schedule_linear: tau is not finite");
+    for (int k = 1; k <= steps; k++) {
+        const double s = (double)k / steps;
+        gamma[k - 1] = tau * s;                                    // tau B(s_k), B(s) = s
+        beta[k - 1] = (paper_sign ? -1.0 : 1.0) * tau * (1.0 - s);  // tau A(s_k) with H_I = -H_D
+    }
+    return SV_OK;
+}
+
+extern "C" int sv_schedule_second_order(int p, double tau, const double* A, const double* B, double* gamma,
+                                        double* beta) {
+    if (p < 2) return fail(SV_ERR_ARG, "sv_schedule_second_order: p=%d < 2 (grid (k-1)/(p-1) undefined)", p);
+    if (!gamma || !beta) return fail(SV_ERR_ARG, "sv_schedule_second_order: NULL output");
+    if (!std::isfinite(tau)) return fail(SV_ERR_NUMERIC, "sv_schedule_second_order: tau is not finite");
+    std::vector<double> a(p), b(p);
+    for (int k = 0; k < p; k++) {
+        const double s = (double)k / (p - 1);
+        a[k] = A ? A[k] : 1.0 - s;
+        b[k] = B ? B[k] : s;
+        if (!std::isfinite(a[k]) || !std::isfinite(b[k]))
+            return fail(SV_ERR_NUMERIC, "sv_schedule_second_order: schedule value %d is not finite", k);
+    }
+    for (int k = 0; k < p; k++) {
+        gamma[k] = tau * b[k];
+        beta[k] = (k + 1 < p) ? -tau * (a[k + 1] + a[k]) / 2.0 : -tau * a[k] / 2.0;
+    }
+    return SV_OK;
+}
+
+// ============================================================================ describe
+extern "C" int sv_tune_describe(int n, sv_dtype dtype, char* buf, size_t len) {
+    if (!buf || len == 0) return fail(SV_ERR_ARG, "sv_tune_describe: empty buffer");
+    if (!dtype_ok(dtype)) return fail(SV_ERR_ARG, "sv_tune_describe: bad dtype");
+    if (n < 1 || n > max_n(dtype)) return fail(SV_ERR_ARG, "sv_tune_describe: bad n");
+    std::string js = "{\"knobs\":{";
+    {
+        std::lock_guard<std::mutex> g(g_knob_mu);
+        bool first = true;
+        for (auto& kv : g_knobs) {
+            js += (first ? "" : ",") + std::string("\"") + kv.first + "\":" + std::to_string(kv.second);
+            first = false;
+        }
+    }
+    js += "},\"plans\":{";
+    for (int nv = 1; nv <= 2; nv++) {
+        std::vector<Geometry> groups = plan_groups(n, dtype, nv);
+        js += std::string(nv == 1 ? "" : ",") + "\"nv" + std::to_string(nv) + "\":[";
+        for (size_t i = 0; i < groups.size(); i++) {
+            const Geometry& g = groups[i];
+            js += (i ? "," : "") + std::string("{\"T\":") + std::to_string(g.T) + ",\"R\":" + std::to_string(g.R) +
+                  ",\"c\":" + std::to_string(g.c) + ",\"lo\":" + std::to_string(g.lo) + ",\"g\":" +
+                  std::to_string(g.g) + ",\"ntiles\":" + std::to_string(g.ntiles) + ",\"phantom\":" +
+                  std::to_string(g.phantom) + ",\"blocks\":[";
+            for (size_t j = 0; j < g.blocks.size(); j++) {
+                js += (j ? "," : "") + std::string("{\"bits\":[");
+                for (size_t k = 0; k < g.blocks[j].size(); k++)
+                    js += (k ? "," : "") + std::to_string(g.blocks[j][k]);
+                js += "],\"fwd\":" + std::to_string(g.act_fwd[j]) + ",\"bwd\":" + std::to_string(g.act_bwd[j]) + "}";
+            }
+            js += "]}";
+        }
+        js += "]";
+    }
+    js += "}}";
+    snprintf(buf, len, "%s", js.c_str());
+    return SV_OK;
+}
+
+extern "C" int sv_batch_p1_scan(int n_inst, const sv_ising* insts, int n_gamma, const double* gammas, int n_beta,
+                                const double* betas, sv_dtype dtype, void* stream, double* energy_out,
+                                double* pgs_out) {
+    (void)n_inst; (void)insts; (void)n_gamma; (void)gammas; (void)n_beta; (void)betas; (void)dtype;
+    (void)stream; (void)energy_out; (void)pgs_out;
+    return fail(SV_ERR_UNSUPPORTED, "sv_batch_p1_scan: not built yet");
+}

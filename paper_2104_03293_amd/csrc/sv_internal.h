@@ -1,0 +1,143 @@
+// Internal structures shared by the host planner (sv_api.cpp) and the gfx950
+// kernels (sv_kernels.hip).  Not part of the public ABI.
+//
+// Vocabulary
+//   tile      : 2^T amplitudes handled by one workgroup in one pass.  Tile-local
+//               bit l maps to global bit P[l]: carriers l < c map to global bits
+//               0..c-1 (contiguous runs of 2^c amplitudes), group bits l >= c map
+//               to global bits lo .. lo+g-1.  Tile-local bits >= n (only when
+//               n < T) are phantom: they address nothing.
+//   layout    : which R tile bits a thread holds in registers (2^R amplitudes per
+//               thread); the other T-R tile bits are the thread index.  A pass
+//               moves the tile through a few layouts via LDS exchanges so that
+//               every active qubit is register-local once.
+//   op        : MIX (one butterfly per active qubit, Eq. twocomponentupdates) or
+//               POINT (work on E(z) in the current layout: phase exp(-i gamma E),
+//               reductions, lambda = E psi, gradient terms).
+#pragma once
+#include <cstdint>
+
+namespace svk {
+
+constexpr int kMaxT = 16;
+constexpr int kMaxR = 6;
+constexpr int kMaxLayouts = 4;
+constexpr int kMaxOps = 16;
+constexpr int kMaxSlots = 8;
+constexpr int kMaxPhase = 4;
+constexpr int kMaxTT = 128;
+constexpr int kMaxTR = 16;
+
+enum OpKind : int32_t { OP_MIX = 1, OP_POINT = 2 };
+
+// MIX flags: which vectors get the butterflies; accumulate grad-beta terms.
+enum MixFlags : int32_t { MIX_PSI = 1, MIX_LAM = 2, MIX_GBETA = 4 };
+
+// POINT flags, executed in this order.
+enum PointFlags : int32_t {
+    PT_REDUCE = 1,     // slots slot, slot+1, slot+2 += |psi|^2, E|psi|^2, [E = Emin]|psi|^2
+    PT_LAM_INIT = 2,   // lam = E psi
+    PT_GGAMMA = 4,     // slot2 += E Im(conj(lam) psi)
+    PT_PHASE_PSI = 8,  // psi *= exp(-i gamma E)
+    PT_PHASE_LAM = 16  // lam *= exp(-i gamma E)
+};
+
+struct Op {
+    int32_t kind;
+    int32_t flags;
+    int32_t slot;   // MIX: grad-beta slot; POINT: first reduce slot
+    int32_t slot2;  // POINT: grad-gamma slot
+    int32_t qidx;   // POINT: index of the (layout, gamma) phase table
+    int32_t pad;
+    double a;       // MIX: cos(beta)   POINT: gamma
+    double b;       // MIX: sin(beta)
+};
+
+// One layout of one tile geometry (device resident, read with uniform loads).
+struct GeoLayout {
+    uint32_t reg_u[64];     // tile-local index of register r (thread part zero)
+    uint32_t reg_lds[64];   // swizzled LDS element index of reg_u[r]
+    uint64_t reg_goff[64];  // global element offset of reg_u[r]
+    int32_t ntb;            // number of thread bits (T - R)
+    int32_t act_fwd;        // register slots butterflied when entering forward
+    int32_t act_bwd;        // ... when walking the layouts backwards
+    int32_t n_tt;           // intra-tile couplings with both ends thread bits
+    int8_t tb[kMaxT];       // thread bits, ascending (thread-id bit j -> tile bit tb[j])
+    int8_t rb[8];           // register bits (register-index bit k -> tile bit rb[k])
+    int32_t n_tr[8];        // per register slot: couplings to thread bits
+    double Q[64];           // sum of couplings among register bits, per register r
+    int8_t tt_a[kMaxTT];
+    int8_t tt_b[kMaxTT];
+    double tt_J[kMaxTT];
+    int8_t tr_l[8][kMaxTR];
+    double tr_J[8][kMaxTR];
+};
+
+struct GeoBuf {
+    int8_t P[kMaxT];  // tile bit -> global bit, -1 = phantom
+    GeoLayout L[kMaxLayouts];
+};
+
+// Device copy of an Ising instance.
+struct IsingDev {
+    const double* h;        // [n]
+    const int32_t* adj_ptr; // [n+1] CSR over both endpoints of every coupling
+    const int32_t* adj_nbr; // [2m]
+    const double* adj_J;    // [2m]
+    const int32_t* ei;      // [m]
+    const int32_t* ej;      // [m]
+    const double* J;        // [m]
+    int32_t n, m;
+};
+
+struct PassArgs {
+    void* psi;
+    void* lam;
+    double* partials;       // [ntiles][nslots]
+    const GeoBuf* geo;
+    IsingDev is;
+    uint64_t ntiles;
+    int32_t n, c, lo, g;    // tile geometry
+    uint32_t phantom;       // tile-local phantom bits
+    int32_t nlayouts;
+    int32_t load;           // bit0 load psi, bit1 load lam, bit2 init psi = |+>
+    int32_t store;          // bit0 store psi, bit1 store lam
+    int32_t nslots;
+    int32_t nops;
+    int32_t nphase;
+    int32_t phase_layout[kMaxPhase];
+    double phase_gamma[kMaxPhase];
+    double emin, etol;      // ground-state test |E - emin| <= etol
+    double amp0;            // 2^{-n/2}
+    Op ops[kMaxOps];
+};
+
+struct GroundArgs {
+    const GeoBuf* geo;
+    IsingDev is;
+    uint64_t ntiles;
+    int32_t n, c, lo, g;
+    uint32_t phantom;
+    int32_t mode;           // 0: minimum energy; 1: count and first index at emin
+    double emin, etol;
+    double* part_e;         // [ntiles]    mode 0
+    uint64_t* part_cnt;     // [ntiles]    mode 1
+    uint64_t* part_arg;     // [ntiles]    mode 1
+};
+
+// Launchers (sv_kernels.hip).  Return hipError_t as int.
+int launch_pass(int dtype, int nv, const PassArgs& a, void* stream);
+int launch_reduce_slots(const double* partials, uint64_t nrows, int nslots, const int* dst,
+                        int accumulate, double* out, void* stream);
+int launch_ground(int dtype, const GroundArgs& a, void* stream);
+int launch_ground_finish(const GroundArgs& a, double* out_e, uint64_t* out_cnt,
+                         uint64_t* out_arg, void* stream);
+int launch_batch_p1(const void* bargs, void* stream);
+
+// Compile-time tile shapes per (dtype, vectors): T tile bits, R register bits.
+struct Shape {
+    int T, R;
+};
+Shape shape_for(int dtype, int nv);
+
+}  // namespace svk

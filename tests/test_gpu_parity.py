@@ -1,0 +1,284 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle.
+
+Tolerances (stated once, used everywhere):
+  complex128 amplitudes  max |psi_gpu - psi_oracle| <= 1e-11
+  complex64  amplitudes  max |psi_gpu - psi_oracle| <= 2e-5
+  energies / probabilities |x_gpu - x_ref| <= 1e-6 * max(|x_ref|, sum|h| + sum|J|)  (energies)
+                           |p_gpu - p_ref| <= 1e-6 (complex128: 1e-11)              (probabilities)
+  gradients  max |g_gpu - g_ref| <= GRAD_TOL[dtype] * max(max|g_ref|, sum|h| + sum|J|)
+             (1e-6 for complex128; 5e-6 for complex64, whose forward and reverse
+             passes each round the amplitudes to f32)
+Sizes span n below the tile (phantom bits), exactly one tile, several tiles in
+one and two groups, and several groups with ragged group widths.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2104_03293_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+AMP_TOL = {"c128": 1e-11, "c64": 2e-5}
+PROB_TOL = {"c128": 1e-11, "c64": 1e-6}
+GRAD_TOL = {"c128": 1e-6, "c64": 5e-6}
+
+
+@pytest.fixture(scope="module")
+def sv():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2104_03293_amd import sv as m
+
+    return m
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    print(f"\n[gpu] {request.node.nodeid}", flush=True)
+    sys.stdout.flush()
+    yield
+
+
+def rand_state(n, seed):
+    rng = np.random.default_rng(seed)
+    v = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    return v / np.linalg.norm(v)
+
+
+def energy_tol(orc, inst, ref):
+    return 1e-6 * max(abs(ref), orc.coeff_scale(inst), 1.0)
+
+
+def instance_for(n, kind, seed):
+    if kind == "int" and n >= 4:
+        return I.degree4_int2(n, seed)
+    if kind == "pm1" and n >= 4:
+        return I.regular3_pm1(n, seed)
+    m = min(2 * n, n * (n - 1) // 2)
+    return I.random_real(n, m, seed)
+
+
+SIZES = [1, 2, 5, 9, 12, 13, 14, 15, 17, 20, 23]
+
+
+# ----------------------------------------------------------------------------- primitives
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 4, 13, 14, 16, 21])
+def test_init_plus(sv, dtype, n):
+    s = sv.State(n, dtype)
+    sv.init_plus(s)
+    got = s.to_numpy()
+    assert np.max(np.abs(got - 2.0 ** (-n / 2))) <= (1e-16 if dtype == "c128" else 1e-8)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", SIZES)
+def test_mixer(sv, orc, dtype, n):
+    psi0 = rand_state(n, 10 + n)
+    s = sv.State(n, dtype)
+    s.from_numpy(psi0)
+    beta = 0.37 + 0.1 * n
+    sv.mixer(s, beta)
+    ref = orc.mixer(n, psi0, beta)
+    assert np.max(np.abs(s.to_numpy() - ref)) <= AMP_TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("kind", ["int", "real"])
+def test_cost_phase(sv, orc, dtype, n, kind):
+    inst = instance_for(n, kind, 20 + n)
+    H = sv.Ising.from_instance(inst)
+    psi0 = rand_state(n, 30 + n)
+    s = sv.State(n, dtype)
+    s.from_numpy(psi0)
+    gamma = -0.83 + 0.05 * n
+    sv.cost_phase(s, H, gamma)
+    ref = orc.cost_phase(inst, psi0, gamma)
+    assert np.max(np.abs(s.to_numpy() - ref)) <= AMP_TOL[dtype]
+
+
+@pytest.mark.parametrize("n", [2, 8, 13, 14, 15, 19, 22])
+@pytest.mark.parametrize("kind", ["int", "real", "pm1"])
+def test_ground(sv, orc, n, kind):
+    inst = instance_for(n, kind, 40 + n)
+    H = sv.Ising.from_instance(inst)
+    got = sv.ground(H)
+    ref = orc.ground(inst)
+    if kind == "real":
+        assert abs(got[0] - ref[0]) <= 1e-12 * max(1.0, orc.coeff_scale(inst))
+    else:
+        assert got[0] == ref[0]
+    assert got[1] == ref[1] and got[2] == ref[2]
+
+
+def test_ground_degenerate(sv, orc):
+    # no fields: every state and its complement share an energy (degeneracy >= 2)
+    inst = I.regular3_pm1(16, 5)
+    inst = dict(inst, h=np.zeros(16))
+    got = sv.ground(sv.Ising.from_instance(inst))
+    ref = orc.ground(inst)
+    assert got == (ref[0], ref[1], ref[2]) and ref[1] >= 2
+
+
+# ----------------------------------------------------------------------------- circuits
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", SIZES)
+@pytest.mark.parametrize("p", [1, 3])
+def test_qaoa_forward_and_expect(sv, orc, dtype, n, p):
+    inst = instance_for(n, "int" if n % 2 else "real", 50 + n)
+    H = sv.Ising.from_instance(inst)
+    g, b = I.uniform_params(p, 60 + n, -1.2, 1.2)
+    s = sv.State(n, dtype)
+    sv.qaoa_forward(s, H, g, b)
+    E = orc.energies(inst)
+    ref = orc.qaoa_state(inst, g, b, E=E)
+    assert np.max(np.abs(s.to_numpy() - ref)) <= AMP_TOL[dtype]
+    en, pgs, nrm = sv.expect(s, H)
+    rn, ren, rpgs = orc.observables(inst, ref, E=E)
+    assert abs(en - ren) <= energy_tol(orc, inst, ren)
+    assert abs(pgs - rpgs) <= PROB_TOL[dtype]
+    assert abs(nrm - 1.0) <= (1e-12 if dtype == "c128" else 1e-5)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [6, 14, 18])
+def test_qaoa_from_given_state(sv, orc, dtype, n):
+    inst = instance_for(n, "int", 70 + n)
+    H = sv.Ising.from_instance(inst)
+    psi0 = rand_state(n, 71 + n)
+    s = sv.State(n, dtype)
+    s.from_numpy(psi0)
+    g, b = [0.3, -0.9], [1.1, 0.4]
+    sv.qaoa_forward(s, H, g, b, from_plus=False)
+    ref = orc.qaoa_state(inst, g, b, psi0=psi0)
+    assert np.max(np.abs(s.to_numpy() - ref)) <= AMP_TOL[dtype]
+
+
+def test_config0(sv, orc):
+    """n = 14, p = 1, gamma = 0.4, beta = 0.3, complex128, 3-regular +-1 instance."""
+    inst = I.config0_instance()
+    H = sv.Ising.from_instance(inst)
+    s = sv.State(14, "c128")
+    sv.qaoa_forward(s, H, [I.CONFIG0_GAMMA], [I.CONFIG0_BETA])
+    E = orc.energies(inst)
+    ref = orc.qaoa_state(inst, [I.CONFIG0_GAMMA], [I.CONFIG0_BETA], E=E)
+    assert np.max(np.abs(s.to_numpy() - ref)) <= 1e-11
+    en, pgs, nrm = sv.expect(s, H)
+    _, ren, rpgs = orc.observables(inst, ref, E=E)
+    assert abs(en - ren) <= 1e-6 * max(abs(ren), orc.coeff_scale(inst))
+    assert abs(pgs - rpgs) <= 1e-11
+    assert sv.ground(H)[:2] == orc.ground(inst, E)[:2]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_fusion_plans_agree(sv, orc, dtype):
+    n = 22 if dtype == "c128" else 24
+    inst = instance_for(n, "int", 80)
+    H = sv.Ising.from_instance(inst)
+    g, b = I.uniform_params(4, 81)
+    a = sv.State(n, dtype)
+    sv.qaoa_forward(a, H, g, b)
+    sv.tune_set("fuse", 0)
+    try:
+        c = sv.State(n, dtype)
+        sv.qaoa_forward(c, H, g, b)
+    finally:
+        sv.tune_set("fuse", 1)
+    assert np.max(np.abs(a.to_numpy() - c.to_numpy())) <= AMP_TOL[dtype] / 10
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_zero_angles_identity(sv, dtype):
+    n = 17
+    inst = instance_for(n, "int", 90)
+    H = sv.Ising.from_instance(inst)
+    s = sv.State(n, dtype)
+    sv.qaoa_forward(s, H, [0.0, 0.0, 0.0], [0.0, 0.0, 0.0])
+    assert np.max(np.abs(s.to_numpy() - 2 ** (-n / 2))) <= (1e-16 if dtype == "c128" else 1e-8)
+
+
+# ----------------------------------------------------------------------------- AQA
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [8, 14, 19])
+def test_aqa_per_step(sv, orc, dtype, n):
+    inst = instance_for(n, "int", 100 + n)
+    H = sv.Ising.from_instance(inst)
+    g, b = orc.aqa_linear_schedule(6, 0.5)
+    s = sv.State(n, dtype)
+    pg, en = sv.aqa_run(s, H, g, b, per_step=True)
+    E = orc.energies(inst)
+    gs = orc.ground(inst, E)
+    psi = orc.plus_state(n)
+    for k in range(6):
+        psi = orc.qaoa_state(inst, g[k:k + 1], b[k:k + 1], psi0=psi, E=E)
+        _, ren, rpg = orc.observables(inst, psi, E=E, gs=gs)
+        assert abs(pg[k] - rpg) <= PROB_TOL[dtype]
+        assert abs(en[k] - ren) <= energy_tol(orc, inst, ren)
+    assert np.max(np.abs(s.to_numpy() - psi)) <= AMP_TOL[dtype]
+
+
+def test_aqa_equals_qaoa_call(sv, orc):
+    """AQA with n steps is one QAOA call with p = n + 1 (Sec. III.B.2)."""
+    n = 16
+    inst = instance_for(n, "int", 110)
+    H = sv.Ising.from_instance(inst)
+    g, b = sv.schedule_second_order(11, 0.4)
+    a = sv.State(n, "c128")
+    sv.aqa_run(a, H, g, b)
+    c = sv.State(n, "c128")
+    sv.qaoa_forward(c, H, g, b)
+    assert np.array_equal(a.to_numpy(), c.to_numpy())
+
+
+# ----------------------------------------------------------------------------- adjoint
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [3, 9, 13, 14, 15, 18, 21])
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_grad_vs_oracle(sv, orc, dtype, n, p):
+    inst = instance_for(n, "int" if n % 2 else "real", 120 + n)
+    H = sv.Ising.from_instance(inst)
+    g, b = I.uniform_params(p, 130 + n + p, -1.0, 1.0)
+    psi = sv.State(n, dtype)
+    lam = sv.State(n, dtype)
+    e, dg, db = sv.grad(psi, lam, H, g, b)
+    f, rg, rb = orc.grad_tangent(inst, g, b)
+    scale = max(np.max(np.abs(np.concatenate([rg, rb]))), orc.coeff_scale(inst))
+    assert abs(e - f) <= energy_tol(orc, inst, f)
+    assert np.max(np.abs(dg - rg)) <= GRAD_TOL[dtype] * scale
+    assert np.max(np.abs(db - rb)) <= GRAD_TOL[dtype] * scale
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_grad_from_forward_state(sv, orc, dtype):
+    n, p = 17, 3
+    inst = instance_for(n, "int", 140)
+    H = sv.Ising.from_instance(inst)
+    g, b = I.linear_ramp_params(p)
+    psi = sv.State(n, dtype)
+    lam = sv.State(n, dtype)
+    sv.qaoa_forward(psi, H, g, b)
+    e, dg, db = sv.grad(psi, lam, H, g, b, psi_is_forward=True)
+    f, rg, rb = orc.grad_tangent(inst, g, b)
+    scale = max(np.max(np.abs(np.concatenate([rg, rb]))), orc.coeff_scale(inst))
+    assert np.max(np.abs(dg - rg)) <= GRAD_TOL[dtype] * scale
+    assert np.max(np.abs(db - rb)) <= GRAD_TOL[dtype] * scale
+
+
+def test_grad_errors(sv):
+    H = sv.Ising.from_instance(instance_for(10, "int", 1))
+    a = sv.State(10, "c128")
+    b = sv.State(10, "c64")
+    with pytest.raises(sv.SVError) as e:
+        sv.grad(a, b, H, [0.1], [0.2])
+    assert e.value.code == 1
+    with pytest.raises(sv.SVError) as e:
+        sv.grad(a, a, H, [0.1], [0.2])
+    assert e.value.code == 1
+    c = sv.State(11, "c128")
+    with pytest.raises(sv.SVError):
+        sv.qaoa_forward(c, H, [0.1], [0.2])
