@@ -41,7 +41,10 @@ def main():
     ap.add_argument("--p", type=int, default=4)
     ap.add_argument("--dtype", default="c128")
     ap.add_argument("--no-extras", action="store_true", help="skip gradient / c64 / CPU-baseline legs")
-    ap.add_argument("--cpu-sample-n", type=int, default=24)
+    ap.add_argument("--cpu-sample-n", type=int, default=28)
+    ap.add_argument("--cpu-sample-p", type=int, default=8)
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="run one plain device-to-device copy of this size first (counter reference)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
@@ -54,6 +57,14 @@ def main():
     from paper_2104_03293_amd import sv
 
     torch.cuda.set_device(0)
+    if args.copy_ref_mib > 0:
+        nel = args.copy_ref_mib << 18  # float32 elements
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] reference copy of {args.copy_ref_mib} MiB done")
+        del src, dst
     n, p = args.n, args.p
     inst = I.config4_instance(n) if n >= 33 else I.degree4_int2(n, 4 + n)
     H = sv.Ising.from_instance(inst)
@@ -132,7 +143,7 @@ def main():
 
     cpu = None
     if not args.no_extras:
-        cpu = cpu_baseline(args.cpu_sample_n, p)
+        cpu = cpu_baseline(args.cpu_sample_n, args.cpu_sample_p)
 
     res = {
         "metric": "amplitude-updates/s per QAOA layer at n=32 (HBM roofline of the layer kernel; grad vs FD)",

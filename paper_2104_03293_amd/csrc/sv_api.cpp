@@ -160,6 +160,8 @@ static void prof_end(hipStream_t st, hipEvent_t a, const std::string& kind, doub
 
 // ============================================================================ objects
 struct Work {
+    double2* d_tab = nullptr;
+    size_t tab_cap = 0;  // double2
     double* d_part = nullptr;
     size_t part_cap = 0;  // doubles
     double* d_res = nullptr;
@@ -192,6 +194,7 @@ struct sv_ising_s {
     std::vector<int32_t> ei, ej;
     bool integer = true;
     double scale = 0.0;
+    int lut_half = -1;  // max(sum|h|+sum|J|, 2 max_k(|h_k| + sum_j |J_kj|)) for integer instances
     // device tables
     double* d_h = nullptr;
     int32_t* d_adj_ptr = nullptr;
@@ -233,11 +236,13 @@ static uint32_t swizzle(uint32_t u, int G) {
 
 static int swz_bits(sv_dtype d) { return d == SV_C128 ? 3 : 4; }
 
-// Register-bit blocks for a geometry: the first layout holds the top R tile
-// bits so that lanes run over tile bits 0..5 (coalesced loads); the low block
-// [0, R) comes second; the remaining active bits are covered from the top with
-// blocks starting at or above the swizzle width, so the last layout again has
-// the carriers as the lowest lane bits (coalesced stores).
+// Register-bit blocks for a geometry.  Every block keeps the pivot (tile bit
+// T-1) in register slot R-1 so that an LDS exchange runs in two halves.  The
+// first layout holds the top R tile bits, leaving tile bits 0..5 to the lanes
+// (coalesced loads); for group A the low block [0, R-1) comes second; the
+// remaining active bits are covered from the top with blocks that start at or
+// above the swizzle width G, so the last layout again has the carriers as its
+// lowest lane bits (coalesced stores).
 static Geometry make_geometry(int n, int T, int R, int c, int lo, int g, int G) {
     Geometry geo{};
     geo.T = T;
@@ -257,38 +262,47 @@ static Geometry make_geometry(int n, int T, int R, int c, int lo, int g, int G) 
     } else {
         for (int l = c; l < T; l++) active |= 1u << l;
     }
-    std::vector<std::pair<int, int>> blk;  // [a, a + R)
-    blk.push_back({T - R, T});
+    const int F = R - 1;  // free (non-pivot) register slots
+    std::vector<std::vector<int>> blk;
+    {
+        std::vector<int> b0;
+        for (int l = T - R; l < T; l++) b0.push_back(l);
+        blk.push_back(b0);
+    }
+    auto add = [&](int a) {
+        std::vector<int> b;
+        for (int l = a; l < a + F; l++) b.push_back(l);
+        b.push_back(T - 1);
+        blk.push_back(b);
+    };
     if (groupA) {
-        blk.push_back({0, R});
+        add(0);
+        // cover [F, T - R) from the top; the last block starts at or above the
+        // swizzle width when it can
         int hi = T - R;
-        while (hi > R) {
-            int a = std::max(hi - R, G);
-            blk.push_back({a, a + R});
+        while (hi > F) {
+            const int a = (hi - F <= F) ? std::max(hi - F, std::min(G, F)) : hi - F;
+            add(a);
             hi = a;
         }
     } else {
         int hi = T - R;
         while (hi > c) {
-            int a = std::max(hi - R, c);
-            blk.push_back({a, a + R});
+            int a = std::max(hi - F, c);
+            add(a);
             hi = a;
         }
     }
     // keep blocks that touch active bits
-    std::vector<std::pair<int, int>> keep;
+    std::vector<std::vector<int>> keep;
     for (auto& b : blk) {
         uint32_t m = 0;
-        for (int l = b.first; l < b.second; l++) m |= 1u << l;
+        for (int l : b) m |= 1u << l;
         if (m & active) keep.push_back(b);
     }
     if (keep.empty()) keep.push_back(blk[0]);
     const int K = (int)keep.size();
-    for (auto& b : keep) {
-        std::vector<int> bits;
-        for (int l = b.first; l < b.second; l++) bits.push_back(l);
-        geo.blocks.push_back(bits);
-    }
+    geo.blocks = keep;
     geo.act_fwd.assign(K, 0);
     geo.act_bwd.assign(K, 0);
     uint32_t done = 0;
@@ -313,8 +327,8 @@ static Geometry make_geometry(int n, int T, int R, int c, int lo, int g, int G) 
 // Tile groups covering all qubits: group A = tile bits 0..T-1 (contiguous),
 // then the bits above T split into near-equal groups of at most T - cmin bits,
 // each tile carrying 2^c contiguous amplitudes (c = T - g >= cmin).
-static std::vector<Geometry> plan_groups(int n, sv_dtype dt, int nv) {
-    const Shape sh = shape_for((int)dt, nv);
+static std::vector<Geometry> plan_groups(int n, sv_dtype dt, int nv, bool grad = false) {
+    const Shape sh = shape_for((int)dt, nv, grad);
     const int T = sh.T, R = sh.R, G = swz_bits(dt);
     std::vector<Geometry> out;
     if (n <= T) {
@@ -374,7 +388,7 @@ static int build_geobuf(const Geometry& geo, const sv_ising_s* H, sv_dtype dt, G
             for (int k = 0; k < R; k++)
                 if (r >> k & 1) u |= 1u << rb[k];
             L.reg_u[r] = u;
-            L.reg_lds[r] = swizzle(u, G);
+            L.reg_lds[r] = swizzle(u & ((1u << (T - 1)) - 1u), G);
             L.reg_goff[r] = (u & geo.phantom) ? 0 : gmap(u);
         }
         if (H) {
@@ -482,13 +496,21 @@ static int point_rank(int flags) {
     return 0;
 }
 
-// Partition events into passes (greedy): a pass keeps one tile group; POINT
-// work joins the open pass; a MIX on another group opens a new pass.
+// Partition events into passes (greedy).  A pass has one tile group and the
+// fixed shape  MIX{0,2} POINT{0,1} MIX{0,2}  (kernel slots 0-1, 2, 3-4).
+// Consecutive POINT events merge into one POINT when the kernel's fixed order
+// (reduce, lambda init, grad-gamma, phase) agrees with the event order.
 static Program build_program(const std::vector<Event>& evs, int nres, bool fuse) {
     Program prog;
     prog.nres = nres;
     Pass cur;
     bool open = false;
+    bool lam_live = false;  // two-vector passes carry at most 4 reduction slots
+    int nmix_pre = 0, nmix_post = 0;
+    bool has_point = false;
+    auto limit = [&](const Event& e) {
+        return (lam_live || e.kind == EV_LAMINIT || (e.vec & 2)) ? 4 : kMaxSlots;
+    };
     auto close = [&]() {
         if (open) prog.passes.push_back(cur);
         cur = Pass();
@@ -497,6 +519,13 @@ static Program build_program(const std::vector<Event>& evs, int nres, bool fuse)
     auto start = [&](int group) {
         cur = Pass();
         cur.group = group;
+        cur.ops.assign(kMaxOps, Op{});
+        for (Op& o : cur.ops) {
+            o.kind = 0;
+            o.slot = o.slot2 = o.qidx = -1;
+        }
+        nmix_pre = nmix_post = 0;
+        has_point = false;
         open = true;
     };
     for (const Event& e : evs) {
@@ -507,28 +536,42 @@ static Program build_program(const std::vector<Event>& evs, int nres, bool fuse)
             continue;
         }
         if (e.kind == EV_MIX) {
+            // exp(-i beta X) = (-1)^k exp(-i beta' X), beta' = beta - k pi in [-pi/2, pi/2];
+            // |beta'| > pi/4 is applied as two halves so that |tan| <= 1.
+            const double kpi = std::nearbyint(e.angle / M_PI);
+            const double bred = e.angle - kpi * M_PI;
+            const double sign = (std::fmod(std::fabs(kpi), 2.0) == 1.0) ? -1.0 : 1.0;
+            const int nhalf = std::fabs(bred) > M_PI / 4 ? 2 : 1;
+            const double bh = bred / nhalf;
             const int slots = e.res >= 0 ? 1 : 0;
             bool can = open && (!cur.has_mix || (cur.group == e.group && fuse)) &&
-                       (int)cur.ops.size() < kMaxOps && (int)cur.slot_dst.size() + slots <= kMaxSlots;
+                       (int)cur.slot_dst.size() + slots <= limit(e);
+            if (can) {
+                if (!has_point) can = nmix_pre + nhalf <= 2;
+                else can = nmix_post + nhalf <= 2;
+            }
             if (!can) {
                 close();
                 start(e.group);
             }
-            cur.group = e.group;  // POINT-only prefixes run in layout 0 of any group
-            Op op{};
-            op.kind = OP_MIX;
-            op.flags = (e.vec & 1 ? MIX_PSI : 0) | (e.vec & 2 ? MIX_LAM : 0);
-            op.slot = -1;
-            op.slot2 = -1;
-            op.qidx = -1;
-            if (e.res >= 0) {
-                op.flags |= MIX_GBETA;
-                op.slot = (int)cur.slot_dst.size();
-                cur.slot_dst.push_back(e.res);
+            cur.group = e.group;  // a POINT-only prefix runs in layout 0 of any group
+            for (int h = 0; h < nhalf; h++) {
+                Op op{};
+                op.kind = OP_MIX;
+                op.flags = (e.vec & 1 ? MIX_PSI : 0) | (e.vec & 2 ? MIX_LAM : 0);
+                op.slot = -1;
+                op.slot2 = -1;
+                op.qidx = -1;
+                if (e.res >= 0 && h == 0) {
+                    op.flags |= MIX_GBETA;
+                    op.slot = (int)cur.slot_dst.size();
+                    cur.slot_dst.push_back(e.res);
+                }
+                op.a = std::tan(bh);
+                op.b = (h == 0 ? sign : 1.0) * std::cos(bh);
+                if (!has_point) cur.ops[nmix_pre++] = op;
+                else cur.ops[3 + nmix_post++] = op;
             }
-            op.a = std::cos(e.angle);
-            op.b = std::sin(e.angle);
-            cur.ops.push_back(op);
             cur.has_mix = true;
             continue;
         }
@@ -537,28 +580,23 @@ static Program build_program(const std::vector<Event>& evs, int nres, bool fuse)
         if (e.kind == EV_REDUCE) flag = PT_REDUCE;
         if (e.kind == EV_LAMINIT) flag = PT_LAM_INIT;
         if (e.kind == EV_GGAMMA) flag = PT_GGAMMA;
-        if (!open || (!fuse && cur.has_mix)) {
-            close();
-            start(0);
-        }
         const int slots = e.kind == EV_REDUCE ? 3 : (e.kind == EV_GGAMMA ? 1 : 0);
-        const bool is_phase = e.kind == EV_PHASE;
-        Op* last = cur.ops.empty() ? nullptr : &cur.ops.back();
-        bool merge = last && last->kind == OP_POINT && !(last->flags & flag);
-        if (merge) {
-            // the kernel runs POINT parts in a fixed order: merge only if that order
-            // agrees with the event order; a reduction reads only |psi|^2 and E, which
-            // a phase does not change, so it may move ahead of a phase.
-            const int mine = point_rank(flag);
-            const int lastmax = point_rank(last->flags);
-            merge = mine > lastmax ||
-                    (flag == PT_REDUCE && !(last->flags & (PT_LAM_INIT | PT_GGAMMA)));
+        bool merge = false;
+        if (open && has_point && nmix_post == 0) {
+            const Op& last = cur.ops[2];
+            merge = !(last.flags & flag);
+            if (merge) {
+                // a reduction reads only |psi|^2 and E, which a phase leaves alone
+                const int mine = point_rank(flag);
+                const int lastmax = point_rank(last.flags);
+                merge = mine > lastmax || (flag == PT_REDUCE && !(last.flags & (PT_LAM_INIT | PT_GGAMMA)));
+            }
         }
-        const bool fits = (int)cur.slot_dst.size() + slots <= kMaxSlots &&
-                          (!is_phase || (int)cur.phase.size() < kMaxPhase) &&
-                          (merge || (int)cur.ops.size() < kMaxOps);
+        bool fits = open && (!fuse ? !cur.has_mix : true) && (int)cur.slot_dst.size() + slots <= limit(e);
+        if (fits && !merge) fits = !has_point;  // a new POINT needs the (single) point slot
+        if (fits && has_point && !merge) fits = false;
         if (!fits) {
-            const int g = cur.has_mix ? cur.group : 0;
+            const int g = (open && cur.has_mix && nmix_post == 0 && !has_point) ? cur.group : 0;
             close();
             start(g);
             merge = false;
@@ -569,9 +607,10 @@ static Program build_program(const std::vector<Event>& evs, int nres, bool fuse)
             op.slot = -1;
             op.slot2 = -1;
             op.qidx = -1;
-            cur.ops.push_back(op);
+            cur.ops[2] = op;
+            has_point = true;
         }
-        Op& op = cur.ops.back();
+        Op& op = cur.ops[2];
         op.flags |= flag;
         if (e.kind == EV_REDUCE) {
             op.slot = (int)cur.slot_dst.size();
@@ -583,6 +622,8 @@ static Program build_program(const std::vector<Event>& evs, int nres, bool fuse)
             op.a = e.angle;
             op.qidx = (int)cur.phase.size();
             cur.phase.push_back({-1, e.angle});
+        } else if (e.kind == EV_LAMINIT) {
+            lam_live = true;
         }
     }
     close();
@@ -612,7 +653,7 @@ static void finalize_program(Program& prog, const std::vector<Geometry>* groups_
         for (Op& op : p.ops) {
             if (op.kind == OP_MIX) {
                 if (K > 1) cur = (cur == 0) ? K - 1 : 0;
-            } else if (op.flags & (PT_PHASE_PSI | PT_PHASE_LAM)) {
+            } else if (op.kind == OP_POINT && (op.flags & (PT_PHASE_PSI | PT_PHASE_LAM))) {
                 p.phase[op.qidx].first = cur;
             }
         }
@@ -666,10 +707,11 @@ struct Plan {
     std::vector<Geometry> by_nv[3];  // [1]: one-vector tile shape, [2]: two-vector shape
 };
 
-static Plan make_plan(int n, sv_dtype dt) {
+// grad: the adjoint family, whose one- and two-vector tiles share T.
+static Plan make_plan(int n, sv_dtype dt, bool grad = false) {
     Plan pl;
-    pl.by_nv[1] = plan_groups(n, dt, 1);
-    pl.by_nv[2] = plan_groups(n, dt, 2);
+    pl.by_nv[1] = plan_groups(n, dt, 1, grad);
+    pl.by_nv[2] = plan_groups(n, dt, 2, grad);
     return pl;
 }
 
@@ -697,7 +739,48 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         }
     }
     const double amp0 = std::pow(2.0, -0.5 * s->n);
-    for (const Pass& p : prog.passes) {
+    // phase tables of every pass, built by one setup launch
+    const int lut_half = H ? H->lut_half : -1;
+    std::vector<TableJob> jobs;
+    std::vector<std::vector<std::pair<uint32_t, uint32_t>>> offs(prog.passes.size());
+    size_t tab_need = 0;
+    for (size_t pi = 0; pi < prog.passes.size(); pi++) {
+        const Pass& p = prog.passes[pi];
+        if (p.phase.empty()) continue;
+        const Geometry& geo = plan.by_nv[p.nv][p.group];
+        GeoBuf* gb = nullptr;
+        rc = get_geobuf(geo, H, s->dt, &gb);
+        if (rc) return rc;
+        for (const auto& ph : p.phase) {
+            TableJob j{};
+            j.gamma = ph.second;
+            j.Q = gb->L[ph.first].Q;  // device address inside the geometry table
+            j.nr = 1 << geo.R;
+            j.L = lut_half;
+            j.qph_off = (uint32_t)tab_need;
+            tab_need += j.nr;
+            j.lut_off = (uint32_t)tab_need;
+            if (lut_half >= 0) tab_need += 2 * lut_half + 1;
+            offs[pi].push_back({j.qph_off, j.lut_off});
+            jobs.push_back(j);
+        }
+    }
+    if (tab_need > s->w.tab_cap) {
+        if (s->w.d_tab) (void)hipFree(s->w.d_tab);
+        s->w.d_tab = nullptr;
+        s->w.tab_cap = 0;
+        HIPCHECK(hipMalloc(&s->w.d_tab, tab_need * sizeof(double2)));
+        s->w.tab_cap = tab_need;
+    }
+    if (!jobs.empty()) {
+        int e = launch_tables(jobs.data(), (int)jobs.size(), s->w.d_tab, s->stream);
+        if (e != 0) {
+            s->failed = true;
+            return fail(SV_ERR_HIP, "table launch failed: %s", hipGetErrorString((hipError_t)e));
+        }
+    }
+    for (size_t pi = 0; pi < prog.passes.size(); pi++) {
+        const Pass& p = prog.passes[pi];
         const Geometry& geo = plan.by_nv[p.nv][p.group];
         if (p.nv == 2 && !lam) return fail(SV_ERR_ARG, "internal: two-vector pass without lam");
         GeoBuf* gb = nullptr;
@@ -720,19 +803,22 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         a.load = p.load;
         a.store = p.store;
         a.nslots = (int)p.slot_dst.size();
-        a.nops = (int)p.ops.size();
+        a.nops = 0;
+        for (const Op& op : p.ops) a.nops += op.kind != 0;
         a.nphase = (int)p.phase.size();
+        a.ptab = s->w.d_tab;
+        a.lut_half = lut_half;
         for (int q = 0; q < a.nphase; q++) {
-            a.phase_layout[q] = p.phase[q].first;
-            a.phase_gamma[q] = p.phase[q].second;
+            a.qph_off[q] = offs[pi][q].first;
+            a.lut_off[q] = offs[pi][q].second;
         }
         a.emin = emin;
         a.etol = etol;
         a.amp0 = amp0;
-        for (int i = 0; i < a.nops; i++) a.ops[i] = p.ops[i];
+        for (int i = 0; i < kMaxOps; i++) a.ops[i] = p.ops[i];
         hipEvent_t ev0;
         const bool prof = prof_begin(s->stream, &ev0);
-        int e = launch_pass((int)s->dt, p.nv, a, s->stream);
+        int e = launch_pass((int)s->dt, p.nv, geo.T, a, s->stream);
         if (prof) {
             const int nrd = (p.load & 4) ? 0 : __builtin_popcount(p.load & 3);
             const int nwr = __builtin_popcount(p.store & 3);
@@ -819,6 +905,7 @@ extern "C" int sv_free(sv_state s) {
     if (!s) return SV_OK;
     if (s->owned && s->ptr) (void)hipFree(s->ptr);
     if (s->w.d_part) (void)hipFree(s->w.d_part);
+    if (s->w.d_tab) (void)hipFree(s->w.d_tab);
     if (s->w.d_res) (void)hipFree(s->w.d_res);
     if (s->w.h_res) (void)hipHostFree(s->w.h_res);
     delete s;
@@ -895,6 +982,17 @@ extern "C" int sv_ising_create(int n, const double* h, int m, const int32_t* ei,
         H->integer = H->integer && v == std::round(v);
         H->scale += std::fabs(v);
     }
+    if (H->integer) {
+        std::vector<double> loc(n, 0.0);
+        for (int i = 0; i < n; i++) loc[i] = std::fabs(H->h[i]);
+        for (int k = 0; k < m; k++) {
+            loc[H->ei[k]] += std::fabs(H->J[k]);
+            loc[H->ej[k]] += std::fabs(H->J[k]);
+        }
+        double L = H->scale;
+        for (double v : loc) L = std::max(L, 2.0 * v);
+        if (L <= 4096.0) H->lut_half = (int)L;
+    }
     // CSR adjacency over both endpoints
     std::vector<int32_t> ptr(n + 1, 0), nbr(2 * m);
     std::vector<double> aj(2 * m);
@@ -950,7 +1048,7 @@ static int run_ground(sv_ising_s* H, hipStream_t stream) {
         if (H->has_ground) return SV_OK;
     }
     const sv_dtype dt = SV_C64;  // enumeration tiles use the complex64 tile shape
-    const Shape sh = shape_for((int)dt, 1);
+    const Shape sh = shape_for((int)dt, 1, false);
     std::vector<Geometry> groups = plan_groups(H->n, dt, 1);
     const Geometry& geo = groups[0];
     GeoBuf* gb = nullptr;
@@ -1165,7 +1263,7 @@ extern "C" int sv_grad(sv_state psi, sv_state lam, sv_ising H, int p, const doub
     if (rc) return rc;
     if (lam->failed) return fail(SV_ERR_HIP, "lam state is in a failed state");
     // both vectors share one tile geometry: plan with the two-vector shape
-    Plan plan = make_plan(psi->n, psi->dt);
+    Plan plan = make_plan(psi->n, psi->dt, true);
     const int G = (int)plan.by_nv[1].size();
     std::vector<Event> ev;
     if (!psi_is_forward) forward_events(ev, G, p, gamma, beta, true, -1);
@@ -1192,24 +1290,21 @@ extern "C" int sv_grad(sv_state psi, sv_state lam, sv_ising H, int p, const doub
     // that result, so psi is not written back.  The final pass writes nothing.
     if (!psi_is_forward) {
         for (Pass& ps : prog.passes) {
-            int fwd = -1, undo = -1, other = 0, laminit = -1;
+            std::vector<const Op*> fw, un;
+            int laminit = -1, phased = 0;
             for (int i = 0; i < (int)ps.ops.size(); i++) {
                 const Op& op = ps.ops[i];
                 if (op.kind == OP_POINT && (op.flags & PT_LAM_INIT)) laminit = i;
-                if (op.kind == OP_POINT && (op.flags & PT_PHASE_PSI)) other++;
-                if (op.kind == OP_MIX && (op.flags & MIX_PSI)) {
-                    if (laminit < 0) {
-                        if (fwd >= 0) other++;
-                        fwd = i;
-                    } else {
-                        if (undo >= 0) other++;
-                        undo = i;
-                    }
-                }
+                if (op.kind == OP_POINT && (op.flags & PT_PHASE_PSI)) phased++;
+                if (op.kind == OP_MIX && (op.flags & MIX_PSI)) (laminit < 0 ? fw : un).push_back(&op);
             }
-            if (laminit >= 0 && fwd >= 0 && undo >= 0 && other == 0 && !ps.init &&
-                ps.ops[fwd].a == ps.ops[undo].a && ps.ops[fwd].b == -ps.ops[undo].b)
-                ps.store &= ~1;
+            bool inverse = laminit >= 0 && !fw.empty() && fw.size() == un.size() && phased == 0 && !ps.init;
+            for (size_t i = 0; inverse && i < fw.size(); i++) {
+                const Op* f = fw[fw.size() - 1 - i];
+                const Op* u = un[i];
+                inverse = (u->a == -f->a) && (std::fabs(u->b) == std::fabs(f->b));
+            }
+            if (inverse) ps.store &= ~1;
         }
     }
     prog.passes.back().store = 0;
@@ -1273,9 +1368,12 @@ extern "C" int sv_tune_describe(int n, sv_dtype dtype, char* buf, size_t len) {
         }
     }
     js += "},\"plans\":{";
-    for (int nv = 1; nv <= 2; nv++) {
-        std::vector<Geometry> groups = plan_groups(n, dtype, nv);
-        js += std::string(nv == 1 ? "" : ",") + "\"nv" + std::to_string(nv) + "\":[";
+    for (int fam = 0; fam < 3; fam++) {
+        const int nv = fam == 2 ? 2 : 1;
+        const bool grad = fam >= 1;
+        std::vector<Geometry> groups = plan_groups(n, dtype, nv, grad);
+        const char* key = fam == 0 ? "nv1" : (fam == 1 ? "grad_nv1" : "grad_nv2");
+        js += std::string(fam == 0 ? "" : ",") + "\"" + key + "\":[";
         for (size_t i = 0; i < groups.size(); i++) {
             const Geometry& g = groups[i];
             js += (i ? "," : "") + std::string("{\"T\":") + std::to_string(g.T) + ",\"R\":" + std::to_string(g.R) +

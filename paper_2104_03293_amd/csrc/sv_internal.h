@@ -10,11 +10,15 @@
 //   layout    : which R tile bits a thread holds in registers (2^R amplitudes per
 //               thread); the other T-R tile bits are the thread index.  A pass
 //               moves the tile through a few layouts via LDS exchanges so that
-//               every active qubit is register-local once.
+//               every active qubit is register-local once.  Register slot R-1
+//               is tile bit T-1 in every layout (the pivot), so an exchange
+//               runs in two halves of 2^(T-1) amplitudes each.
 //   op        : MIX (one butterfly per active qubit, Eq. twocomponentupdates) or
 //               POINT (work on E(z) in the current layout: phase exp(-i gamma E),
 //               reductions, lambda = E psi, gradient terms).
 #pragma once
+#include <hip/hip_runtime.h>
+
 #include <cstdint>
 
 namespace svk {
@@ -22,7 +26,7 @@ namespace svk {
 constexpr int kMaxT = 16;
 constexpr int kMaxR = 6;
 constexpr int kMaxLayouts = 4;
-constexpr int kMaxOps = 16;
+constexpr int kMaxOps = 5;  // fixed pass shape: MIX MIX POINT MIX MIX
 constexpr int kMaxSlots = 8;
 constexpr int kMaxPhase = 4;
 constexpr int kMaxTT = 128;
@@ -31,6 +35,10 @@ constexpr int kMaxTR = 16;
 enum OpKind : int32_t { OP_MIX = 1, OP_POINT = 2 };
 
 // MIX flags: which vectors get the butterflies; accumulate grad-beta terms.
+// Every MIX applies (u, v) <- (u - i a v, v - i a u) per active qubit, with
+// a = tan(beta') for |beta'| <= pi/4, and multiplies the vector's uniform
+// pending scale by b = +-cos(beta') per qubit (the host reduces beta modulo pi
+// and splits larger angles into two halves).
 enum MixFlags : int32_t { MIX_PSI = 1, MIX_LAM = 2, MIX_GBETA = 4 };
 
 // POINT flags, executed in this order.
@@ -39,7 +47,7 @@ enum PointFlags : int32_t {
     PT_LAM_INIT = 2,   // lam = E psi
     PT_GGAMMA = 4,     // slot2 += E Im(conj(lam) psi)
     PT_PHASE_PSI = 8,  // psi *= exp(-i gamma E)
-    PT_PHASE_LAM = 16  // lam *= exp(-i gamma E)
+    PT_PHASE_LAM = 16  // lam *= exp(-i gamma E); two-vector passes phase both or neither
 };
 
 struct Op {
@@ -49,14 +57,14 @@ struct Op {
     int32_t slot2;  // POINT: grad-gamma slot
     int32_t qidx;   // POINT: index of the (layout, gamma) phase table
     int32_t pad;
-    double a;       // MIX: cos(beta)   POINT: gamma
-    double b;       // MIX: sin(beta)
+    double a;       // MIX: tan(beta')   POINT: gamma
+    double b;       // MIX: +-cos(beta')
 };
 
 // One layout of one tile geometry (device resident, read with uniform loads).
 struct GeoLayout {
     uint32_t reg_u[64];     // tile-local index of register r (thread part zero)
-    uint32_t reg_lds[64];   // swizzled LDS element index of reg_u[r]
+    uint32_t reg_lds[64];   // swizzled LDS element index of reg_u[r] without the pivot bit
     uint64_t reg_goff[64];  // global element offset of reg_u[r]
     int32_t ntb;            // number of thread bits (T - R)
     int32_t act_fwd;        // register slots butterflied when entering forward
@@ -90,10 +98,23 @@ struct IsingDev {
     int32_t n, m;
 };
 
+// Per-call phase tables, built once by k_tables before the passes:
+//   qph: exp(-i gamma Q[r]) for the register-bit couplings of one layout
+//   lut: exp(-i gamma m) for integer m in [-L, L] (integer-valued instances)
+struct TableJob {
+    double gamma;
+    const double* Q;        // device: the layout's Q[64]
+    int32_t nr;             // registers per thread (2^R)
+    int32_t L;              // lut half width (-1: no lut)
+    uint32_t qph_off;       // double2 offset of qph in the table buffer
+    uint32_t lut_off;       // double2 offset of lut[0] (the entry for m = -L)
+};
+
 struct PassArgs {
     void* psi;
     void* lam;
     double* partials;       // [ntiles][nslots]
+    const double2* ptab;    // phase tables (k_tables output)
     const GeoBuf* geo;
     IsingDev is;
     uint64_t ntiles;
@@ -103,10 +124,11 @@ struct PassArgs {
     int32_t load;           // bit0 load psi, bit1 load lam, bit2 init psi = |+>
     int32_t store;          // bit0 store psi, bit1 store lam
     int32_t nslots;
-    int32_t nops;
+    int32_t nops;           // informational; ops[i].kind == 0 marks an absent slot
     int32_t nphase;
-    int32_t phase_layout[kMaxPhase];
-    double phase_gamma[kMaxPhase];
+    int32_t lut_half;       // L of the integer phase tables, -1 for real-valued instances
+    uint32_t qph_off[kMaxPhase];
+    uint32_t lut_off[kMaxPhase];
     double emin, etol;      // ground-state test |E - emin| <= etol
     double amp0;            // 2^{-n/2}
     Op ops[kMaxOps];
@@ -126,7 +148,8 @@ struct GroundArgs {
 };
 
 // Launchers (sv_kernels.hip).  Return hipError_t as int.
-int launch_pass(int dtype, int nv, const PassArgs& a, void* stream);
+int launch_pass(int dtype, int nv, int T, const PassArgs& a, void* stream);
+int launch_tables(const TableJob* jobs, int njobs, double2* out, void* stream);
 int launch_reduce_slots(const double* partials, uint64_t nrows, int nslots, const int* dst,
                         int accumulate, double* out, void* stream);
 int launch_ground(int dtype, const GroundArgs& a, void* stream);
@@ -138,6 +161,6 @@ int launch_batch_p1(const void* bargs, void* stream);
 struct Shape {
     int T, R;
 };
-Shape shape_for(int dtype, int nv);
+Shape shape_for(int dtype, int nv, bool grad);
 
 }  // namespace svk

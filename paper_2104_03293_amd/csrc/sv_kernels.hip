@@ -121,31 +121,112 @@ __device__ __forceinline__ double thread_energy(const GeoLayout* L, uint32_t thr
     return eth;
 }
 
-__device__ __forceinline__ void slot_add(double* acc, int slot, double v) {
+// Wave-level sum of a per-lane value (fixed butterfly order), added by lane 0
+// to this wave's row of the per-workgroup reduction array.
+template <int NS>
+__device__ __forceinline__ void wave_add(double (*s_red)[NS], int slot, double v) {
 #pragma unroll
-    for (int s = 0; s < kMaxSlots; s++)
-        if (s == slot) acc[s] += v;
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6][slot] += v;
 }
 
 __device__ __forceinline__ double2 cmul(double2 x, double2 y) {
     return make_double2(x.x * y.x - x.y * y.y, x.x * y.y + x.y * y.x);
 }
 
-template <typename Real, int T, int R, int NV>
-__global__ void __launch_bounds__(1 << (T - R)) k_pass(const PassArgs a) {
+// One pair butterfly of exp(-i beta sigma^x) without its cos(beta) factor:
+// (u, v) <- (u - i t v, v - i t u), t = tan(beta).
+template <typename Real>
+__device__ __forceinline__ void butterfly(Real& ar, Real& ai, Real& br, Real& bi, Real t) {
+    const Real nar = fma(t, bi, ar), nai = fma(-t, br, ai);
+    const Real nbr = fma(t, ai, br), nbi = fma(-t, ar, bi);
+    ar = nar;
+    ai = nai;
+    br = nbr;
+    bi = nbi;
+}
+
+// Butterflies of every active register slot of the current layout; each slot
+// multiplies the pending scale of the touched vectors by cos(beta).  With
+// gradient accumulation the pair terms Im(conj(lam_a) psi_b) + Im(conj(lam_b) psi_a)
+// are taken before each slot's butterfly, weighted by both pending scales.
+template <typename Real, int R, int NV>
+__device__ __forceinline__ void mix_round(Real (&vr)[NV][1 << R], Real (&vi)[NV][1 << R], int act, int flags,
+                                          Real t, double cosb, double (&pend)[NV], double& gsum) {
+    constexpr int NR = 1 << R;
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        // inactive slots run as identity butterflies (t = 0, no scale): branch-free
+        // code keeps the amplitude registers in place
+        const bool on = (act >> k) & 1;
+        const Real tk = on ? t : (Real)0;
+        if constexpr (NV == 2) {
+            if ((flags & MIX_GBETA) && on) {
+                double gb = 0.0;
+#pragma unroll
+                for (int r = 0; r < NR; r++) {
+                    if (r & (1 << k)) continue;
+                    const int r2 = r | (1 << k);
+                    // pair term in the storage precision, summed in FP64
+                    const Real q = vr[1][r] * vi[0][r2] - vi[1][r] * vr[0][r2] + vr[1][r2] * vi[0][r] -
+                                   vi[1][r2] * vr[0][r];
+                    gb += (double)q;
+                }
+                gsum += gb * pend[0] * pend[1];
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            if (!(flags & (1 << v))) continue;
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                if (r & (1 << k)) continue;
+                const int r2 = r | (1 << k);
+                butterfly<Real>(vr[v][r], vi[v][r], vr[v][r2], vi[v][r2], tk);
+            }
+            pend[v] *= on ? cosb : 1.0;
+        }
+    }
+}
+
+// Phase tables of one call: qph[r] = exp(-i gamma Q[r]) and, for integer-valued
+// instances, lut[m + L] = exp(-i gamma m), m = -L..L.  One workgroup per job.
+struct TableJobs {
+    TableJob j[64];
+};
+
+__global__ void __launch_bounds__(256) k_tables(const TableJobs jobs, double2* __restrict__ out) {
+    const TableJob jb = jobs.j[blockIdx.x];
+    for (int r = threadIdx.x; r < jb.nr; r += 256) {
+        double sn, cs;
+        sincos(jb.gamma * jb.Q[r], &sn, &cs);
+        out[jb.qph_off + r] = make_double2(cs, -sn);
+    }
+    if (jb.L >= 0) {
+        for (int m = threadIdx.x; m <= 2 * jb.L; m += 256) {
+            double sn, cs;
+            sincos(jb.gamma * (double)(m - jb.L), &sn, &cs);
+            out[jb.lut_off + m] = make_double2(cs, -sn);
+        }
+    }
+}
+
+// KC > 0: the pass geometry has exactly KC layouts (compile time, straight-line
+// layout walks); KC == 0: generic kernel with a runtime layout count (used for
+// states smaller than one tile and for real-valued instances).
+template <typename Real, int T, int R, int NV, int NS, int MINB, bool PH, bool INTE, int KC>
+__global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
     using V2 = typename V2T<Real>::type;
     constexpr int NT = 1 << (T - R);
     constexpr int NR = 1 << R;
+    constexpr int NH = NR / 2;  // registers per pivot half
     constexpr int NW = NT / 64;
     constexpr int G = (sizeof(Real) == 8) ? 3 : 4;
-    constexpr int RLO = (R + 1) / 2;
-    constexpr int RHI = R - RLO;
 
-    __shared__ V2 xbuf[1 << T];
+    __shared__ V2 xbuf[1 << (T - 1)];
     __shared__ double s_g[kMaxT];
     __shared__ double s_ew;
-    __shared__ double2 s_qph[kMaxPhase][NR];
-    __shared__ double s_red[NW][kMaxSlots];
+    __shared__ double s_red[NW][NS];
 
     const uint32_t t = threadIdx.x;
     const uint64_t tile = blockIdx.x;
@@ -155,15 +236,8 @@ __global__ void __launch_bounds__(1 << (T - R)) k_pass(const PassArgs a) {
     V2* __restrict__ psi = reinterpret_cast<V2*>(a.psi);
     V2* __restrict__ lam = reinterpret_cast<V2*>(a.lam);
 
-    // ---- prologue: tile fields and phase tables of the couplings among register bits
+    // ---- prologue: fields seen by the tile bits
     if (t < 64) tile_fields(a.is, geo, tg, base, T, s_g, &s_ew);
-    for (int idx = t; idx < a.nphase * NR; idx += NT) {
-        const int q = idx / NR, r = idx % NR;
-        const double th = a.phase_gamma[q] * geo->L[a.phase_layout[q]].Q[r];
-        double sn, cs;
-        sincos(th, &sn, &cs);
-        s_qph[q][r] = make_double2(cs, -sn);
-    }
 
     // ---- load in layout 0
     int cur = 0;
@@ -172,71 +246,104 @@ __global__ void __launch_bounds__(1 << (T - R)) k_pass(const PassArgs a) {
     uint64_t thr_goff = tg.gmap(thr_u);
 
     Real vr[NV][NR], vi[NV][NR];
+    // Phantom bits exist only for states smaller than one tile (PH); full tiles
+    // load without per-register tests.
+    if (a.load & 4) {
 #pragma unroll
-    for (int r = 0; r < NR; r++) {
-        const uint32_t u = thr_u | L->reg_u[r];
-        const bool valid = (u & a.phantom) == 0u;
-        const uint64_t z = base | thr_goff | L->reg_goff[r];
-        Real xr = 0, xi = 0;
-        if (valid) {
-            if (a.load & 4) {
-                xr = (Real)a.amp0;
-            } else if (a.load & 1) {
-                const V2 v = psi[z];
-                xr = v.x;
-                xi = v.y;
-            }
+        for (int r = 0; r < NR; r++) {
+            bool valid = true;
+            if constexpr (PH) valid = ((thr_u | L->reg_u[r]) & a.phantom) == 0u;
+            vr[0][r] = valid ? (Real)a.amp0 : (Real)0;
+            vi[0][r] = 0;
         }
-        vr[0][r] = xr;
-        vi[0][r] = xi;
-        if constexpr (NV == 2) {
-            Real yr = 0, yi = 0;
-            if (valid && (a.load & 2)) {
-                const V2 v = lam[z];
-                yr = v.x;
-                yi = v.y;
+    } else if (a.load & 1) {
+        const V2* __restrict__ src = psi + (base | thr_goff);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            V2 v;
+            if constexpr (PH) {
+                v.x = 0;
+                v.y = 0;
+                if (((thr_u | L->reg_u[r]) & a.phantom) == 0u) v = src[L->reg_goff[r]];
+            } else {
+                v = src[L->reg_goff[r]];
             }
-            vr[1][r] = yr;
-            vi[1][r] = yi;
+            vr[0][r] = v.x;
+            vi[0][r] = v.y;
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            vr[0][r] = 0;
+            vi[0][r] = 0;
+        }
+    }
+    if constexpr (NV == 2) {
+        const V2* __restrict__ src = lam + (base | thr_goff);
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            V2 v;
+            v.x = 0;
+            v.y = 0;
+            bool ok = (a.load & 2) != 0;
+            if constexpr (PH) ok = ok && ((thr_u | L->reg_u[r]) & a.phantom) == 0u;
+            if (ok) v = src[L->reg_goff[r]];
+            vr[1][r] = v.x;
+            vi[1][r] = v.y;
         }
     }
 
-    double acc[kMaxSlots];
+    if ((t & 63) == 0) {
 #pragma unroll
-    for (int s = 0; s < kMaxSlots; s++) acc[s] = 0.0;
+        for (int q = 0; q < NS; q++) s_red[t >> 6][q] = 0.0;
+    }
+    double pend[NV];  // uniform scale every register of vector v still has to be multiplied by
+#pragma unroll
+    for (int v = 0; v < NV; v++) pend[v] = 1.0;
 
-    __syncthreads();  // s_g, s_ew, s_qph ready
+    __syncthreads();  // s_g, s_ew ready
 
-    for (int oi = 0; oi < a.nops; oi++) {
+    // The pass program has a fixed shape: two mixer slots, one point slot, two
+    // mixer slots (absent slots have kind 0).  A compile-time shape keeps the
+    // amplitude registers in place across ops.
+    constexpr int SLOT_KIND[kMaxOps] = {OP_MIX, OP_MIX, OP_POINT, OP_MIX, OP_MIX};
+#pragma unroll
+    for (int oi = 0; oi < kMaxOps; oi++) {
         const Op op = a.ops[oi];
-        if (op.kind == OP_MIX) {
-            const int K = a.nlayouts;
+        if (op.kind == 0) continue;
+        if (SLOT_KIND[oi] == OP_MIX) {
+            const int K = KC > 0 ? KC : a.nlayouts;
             const bool fwd = (cur == 0);
-            const Real c = (Real)op.a, s = (Real)op.b;
-            for (int step = 0; step < K; step++) {
+            double gsum = 0.0;
+            auto round = [&](int step) {
                 const int j = fwd ? step : (K - 1 - step);
-                if (j != cur) {
-                    // LDS exchange cur -> j, one vector at a time
+                if (step > 0) {
+                    // LDS exchange cur -> j in two halves (pivot register slot R-1)
                     const GeoLayout* Lt = &geo->L[j];
                     const uint32_t new_u = thread_index_bits(t, Lt);
                     const uint32_t src = lds_swizzle(thr_u, G);
                     const uint32_t dst = lds_swizzle(new_u, G);
 #pragma unroll
                     for (int v = 0; v < NV; v++) {
-                        __syncthreads();
 #pragma unroll
-                        for (int r = 0; r < NR; r++) {
-                            V2 x;
-                            x.x = vr[v][r];
-                            x.y = vi[v][r];
-                            xbuf[src ^ L->reg_lds[r]] = x;
-                        }
-                        __syncthreads();
+                        for (int h = 0; h < 2; h++) {
+                            __syncthreads();
 #pragma unroll
-                        for (int r = 0; r < NR; r++) {
-                            const V2 x = xbuf[dst ^ Lt->reg_lds[r]];
-                            vr[v][r] = x.x;
-                            vi[v][r] = x.y;
+                            for (int q = 0; q < NH; q++) {
+                                const int r = h * NH + q;
+                                V2 x;
+                                x.x = vr[v][r];
+                                x.y = vi[v][r];
+                                xbuf[src ^ L->reg_lds[r]] = x;
+                            }
+                            __syncthreads();
+#pragma unroll
+                            for (int q = 0; q < NH; q++) {
+                                const int r = h * NH + q;
+                                const V2 x = xbuf[dst ^ Lt->reg_lds[r]];
+                                vr[v][r] = x.x;
+                                vi[v][r] = x.y;
+                            }
                         }
                     }
                     cur = j;
@@ -245,58 +352,35 @@ __global__ void __launch_bounds__(1 << (T - R)) k_pass(const PassArgs a) {
                     thr_goff = tg.gmap(thr_u);
                 }
                 const int act = fwd ? L->act_fwd : L->act_bwd;
-                double gb = 0.0;
+                mix_round<Real, R, NV>(vr, vi, act, op.flags, (Real)op.a, op.b, pend, gsum);
+            };
+            if constexpr (KC > 0) {
 #pragma unroll
-                for (int k = 0; k < R; k++) {
-                    if (!(act & (1 << k))) continue;
-#pragma unroll
-                    for (int r = 0; r < NR; r++) {
-                        if (r & (1 << k)) continue;
-                        const int r2 = r | (1 << k);
-                        if constexpr (NV == 2) {
-                            if (op.flags & MIX_GBETA) {
-                                // Im(conj(lam_a) psi_b) + Im(conj(lam_b) psi_a)
-                                gb += (double)vr[1][r] * (double)vi[0][r2] - (double)vi[1][r] * (double)vr[0][r2] +
-                                      (double)vr[1][r2] * (double)vi[0][r] - (double)vi[1][r2] * (double)vr[0][r];
-                            }
-                        }
-#pragma unroll
-                        for (int v = 0; v < NV; v++) {
-                            if (!(op.flags & (1 << v))) continue;
-                            const Real ar = vr[v][r], ai = vi[v][r];
-                            const Real br = vr[v][r2], bi = vi[v][r2];
-                            vr[v][r] = c * ar + s * bi;
-                            vi[v][r] = c * ai - s * br;
-                            vr[v][r2] = c * br + s * ai;
-                            vi[v][r2] = c * bi - s * ar;
-                        }
-                    }
-                }
-                if constexpr (NV == 2) {
-                    if (op.flags & MIX_GBETA) slot_add(acc, op.slot, gb);
-                }
+                for (int step = 0; step < KC; step++) round(step);
+            } else {
+                for (int step = 0; step < K; step++) round(step);
+            }
+            if constexpr (NV == 2) {
+                if (op.flags & MIX_GBETA) wave_add<NS>(s_red, op.slot, gsum);
             }
         } else {  // OP_POINT
+            // Walk the registers in Gray-code order: consecutive registers differ in
+            // one bit k, so E changes by +-2 f[k] and the phase by exp(-+2i gamma f[k]).
             double f[R];
             const double e0 = thread_energy<R>(L, thr_u, s_g, s_ew, f);
-            double elo[1 << RLO], ehi[1 << RHI];
-            elo[0] = e0;
-#pragma unroll
-            for (int k = 0; k < RLO; k++)
-#pragma unroll
-                for (int r = 0; r < (1 << k); r++) elo[r | (1 << k)] = elo[r] + 2.0 * f[k];
-            ehi[0] = 0.0;
-#pragma unroll
-            for (int k = 0; k < RHI; k++)
-#pragma unroll
-                for (int r = 0; r < (1 << k); r++) ehi[r | (1 << k)] = ehi[r] + 2.0 * f[RLO + k];
-
             const int fl = op.flags;
+            // E of register r = e0 + (Gray-walk sum of +-2 f[k]) + Q[r]
             if (fl & (PT_REDUCE | PT_LAM_INIT | PT_GGAMMA)) {
                 double r_n = 0.0, r_e = 0.0, r_p = 0.0, r_g = 0.0;
+                double e_run = e0;
 #pragma unroll
-                for (int r = 0; r < NR; r++) {
-                    const double e = elo[r & ((1 << RLO) - 1)] + ehi[r >> RLO] + L->Q[r];
+                for (int i = 0; i < NR; i++) {
+                    const int r = i ^ (i >> 1);
+                    if (i > 0) {
+                        const int k = __builtin_ctz(i);
+                        e_run += ((r >> k) & 1) ? 2.0 * f[k] : -2.0 * f[k];
+                    }
+                    const double e = e_run + L->Q[r];
                     const double pr = (double)vr[0][r], pi = (double)vi[0][r];
                     if (fl & PT_REDUCE) {
                         const double p2 = pr * pr + pi * pi;
@@ -309,97 +393,103 @@ __global__ void __launch_bounds__(1 << (T - R)) k_pass(const PassArgs a) {
                             vr[1][r] = (Real)(e * pr);
                             vi[1][r] = (Real)(e * pi);
                         }
-                        if (fl & PT_GGAMMA) r_g += e * ((double)vr[1][r] * pi - (double)vi[1][r] * pr);
+                        if (fl & PT_GGAMMA) {
+                            const Real q = vr[1][r] * vi[0][r] - vi[1][r] * vr[0][r];
+                            r_g += e * (double)q;
+                        }
                     }
                 }
                 if (fl & PT_REDUCE) {
-                    slot_add(acc, op.slot, r_n);
-                    slot_add(acc, op.slot + 1, r_e);
-                    slot_add(acc, op.slot + 2, r_p);
+                    const double s2 = pend[0] * pend[0];
+                    wave_add<NS>(s_red, op.slot, r_n * s2);
+                    wave_add<NS>(s_red, op.slot + 1, r_e * s2);
+                    wave_add<NS>(s_red, op.slot + 2, r_p * s2);
                 }
-                if (fl & PT_GGAMMA) slot_add(acc, op.slot2, r_g);
+                if constexpr (NV == 2) {
+                    if (fl & PT_LAM_INIT) pend[1] = pend[0];
+                    if (fl & PT_GGAMMA) wave_add<NS>(s_red, op.slot2, r_g * pend[0] * pend[1]);
+                }
             }
             if (fl & (PT_PHASE_PSI | PT_PHASE_LAM)) {
                 const double gam = op.a;
-                double2 plo[1 << RLO], phi[1 << RHI];
-                {
+                const double2* __restrict__ qph = a.ptab + a.qph_off[op.qidx];
+                double2 gk[R];
+                double2 run;
+                if constexpr (INTE) {
+                    // integer energies: factors from the table exp(-i gamma m)
+                    const double2* __restrict__ lut = a.ptab + a.lut_off[op.qidx] + a.lut_half;
+                    const int Lh = a.lut_half;
+#pragma unroll
+                    for (int k = 0; k < R; k++) {
+                        const int m = min(max((int)(2.0 * f[k]), -Lh), Lh);
+                        gk[k] = lut[m];
+                    }
+                    run = lut[min(max((int)e0, -Lh), Lh)];
+                } else {
+#pragma unroll
+                    for (int k = 0; k < R; k++) {
+                        double sn, cs;
+                        sincos(2.0 * gam * f[k], &sn, &cs);
+                        gk[k] = make_double2(cs, -sn);
+                    }
                     double sn, cs;
                     sincos(gam * e0, &sn, &cs);
-                    plo[0] = make_double2(cs, -sn);
+                    run = make_double2(cs, -sn);
                 }
+                double fac[NV];
 #pragma unroll
-                for (int k = 0; k < RLO; k++) {
-                    double sn, cs;
-                    sincos(2.0 * gam * f[k], &sn, &cs);
-                    const double2 gk = make_double2(cs, -sn);
+                for (int v = 0; v < NV; v++) fac[v] = pend[v];
 #pragma unroll
-                    for (int r = 0; r < (1 << k); r++) plo[r | (1 << k)] = cmul(plo[r], gk);
-                }
-                phi[0] = make_double2(1.0, 0.0);
-#pragma unroll
-                for (int k = 0; k < RHI; k++) {
-                    double sn, cs;
-                    sincos(2.0 * gam * f[RLO + k], &sn, &cs);
-                    const double2 gk = make_double2(cs, -sn);
-#pragma unroll
-                    for (int r = 0; r < (1 << k); r++) phi[r | (1 << k)] = cmul(phi[r], gk);
-                }
-#pragma unroll
-                for (int r = 0; r < NR; r++) {
-                    const double2 ph = cmul(cmul(plo[r & ((1 << RLO) - 1)], phi[r >> RLO]), s_qph[op.qidx][r]);
+                for (int i = 0; i < NR; i++) {
+                    const int r = i ^ (i >> 1);
+                    if (i > 0) {
+                        const int k = __builtin_ctz(i);
+                        const double2 g = ((r >> k) & 1) ? gk[k] : make_double2(gk[k].x, -gk[k].y);
+                        run = cmul(run, g);
+                    }
+                    const double2 ph = cmul(run, qph[r]);
 #pragma unroll
                     for (int v = 0; v < NV; v++) {
-                        if (!(fl & (v == 0 ? PT_PHASE_PSI : PT_PHASE_LAM))) continue;
+                        const double pr = ph.x * fac[v], pim = ph.y * fac[v];
                         if constexpr (sizeof(Real) == 8) {
                             const double xr = vr[v][r], xi = vi[v][r];
-                            vr[v][r] = xr * ph.x - xi * ph.y;
-                            vi[v][r] = xr * ph.y + xi * ph.x;
+                            vr[v][r] = xr * pr - xi * pim;
+                            vi[v][r] = xr * pim + xi * pr;
                         } else {
-                            const float cr = (float)ph.x, ci = (float)ph.y;
+                            const float cr = (float)pr, ci = (float)pim;
                             const float xr = vr[v][r], xi = vi[v][r];
                             vr[v][r] = xr * cr - xi * ci;
                             vi[v][r] = xr * ci + xi * cr;
                         }
                     }
                 }
+#pragma unroll
+                for (int v = 0; v < NV; v++) pend[v] = 1.0;
             }
         }
     }
 
-    // ---- store in the current layout
-    if (a.store) {
+    // ---- store in the current layout (applying what is left of the pending scales)
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        if (!(a.store & (1 << v))) continue;
+        V2* __restrict__ dst = (v == 0 ? psi : lam) + (base | thr_goff);
+        const Real sc = (Real)pend[v];
+        const bool unit = pend[v] == 1.0;
 #pragma unroll
         for (int r = 0; r < NR; r++) {
-            const uint32_t u = thr_u | L->reg_u[r];
-            if ((u & a.phantom) != 0u) continue;
-            const uint64_t z = base | thr_goff | L->reg_goff[r];
-            if (a.store & 1) {
-                V2 x;
-                x.x = vr[0][r];
-                x.y = vi[0][r];
-                psi[z] = x;
+            if constexpr (PH) {
+                if (((thr_u | L->reg_u[r]) & a.phantom) != 0u) continue;
             }
-            if constexpr (NV == 2) {
-                if (a.store & 2) {
-                    V2 x;
-                    x.x = vr[1][r];
-                    x.y = vi[1][r];
-                    lam[z] = x;
-                }
-            }
+            V2 x;
+            x.x = unit ? vr[v][r] : vr[v][r] * sc;
+            x.y = unit ? vi[v][r] : vi[v][r] * sc;
+            dst[L->reg_goff[r]] = x;
         }
     }
 
     // ---- per-tile partial sums, fixed order
     if (a.nslots > 0) {
-        const int lane = t & 63, w = t >> 6;
-#pragma unroll
-        for (int s = 0; s < kMaxSlots; s++) {
-            double v = acc[s];
-#pragma unroll
-            for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
-            if (lane == 0) s_red[w][s] = v;
-        }
         __syncthreads();
         if ((int)t < a.nslots) {
             double v = 0.0;
@@ -557,25 +647,64 @@ __global__ void __launch_bounds__(256) k_ground_finish(const GroundArgs a, doubl
 }
 
 // ----------------------------------------------------------------------------- dispatch
-Shape shape_for(int dtype, int nv) {
+// Tile shapes.  complex128: T = 13 (128 KiB tiles).  complex64: T = 14 for
+// one-vector programs; adjoint programs use T = 13 for both vectors, the
+// largest two-vector tile whose kernel fits the register file.
+Shape shape_for(int dtype, int nv, bool grad) {
     if (dtype == 2) return nv == 1 ? Shape{13, 5} : Shape{13, 4};
-    return Shape{14, 5};
+    if (!grad) return Shape{14, 5};
+    return nv == 1 ? Shape{13, 5} : Shape{13, 4};
 }
 
-template <typename Real, int T, int R, int NV>
+// Slot counts: one-vector passes carry up to 8 reduction slots (fused AQA
+// steps); two-vector passes need at most 4 (3 for the turnaround reductions
+// + 1 gradient slot, or 3 gradient slots).
+template <typename Real, int T, int R, int NV, int NS, int MINB>
 static int run_pass(const PassArgs& a, void* stream) {
-    hipLaunchKernelGGL((k_pass<Real, T, R, NV>), dim3((unsigned)a.ntiles), dim3(1 << (T - R)), 0,
-                       (hipStream_t)stream, a);
+    const dim3 grid((unsigned)a.ntiles), block(1 << (T - R));
+    hipStream_t st = (hipStream_t)stream;
+    const bool fast = a.phantom == 0 && (a.lut_half >= 0 || a.nphase == 0);
+    if (fast) {
+        // one or two layouts: straight-line walks; three or more: a loop keeps
+        // the register pressure below the two-workgroups-per-CU limit
+        if (a.nlayouts == 1)
+            hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 1>), grid, block, 0, st, a);
+        else if (a.nlayouts == 2)
+            hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 2>), grid, block, 0, st, a);
+        else
+            hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 0>), grid, block, 0, st, a);
+    } else if (a.lut_half >= 0) {
+        hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, true, true, 0>), grid, block, 0, st, a);
+    } else {
+        hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, true, false, 0>), grid, block, 0, st, a);
+    }
     return (int)hipGetLastError();
 }
 
-int launch_pass(int dtype, int nv, const PassArgs& a, void* stream) {
+int launch_pass(int dtype, int nv, int T, const PassArgs& a, void* stream) {
+    if (nv == 2 && a.nslots > 4) return (int)hipErrorInvalidValue;
+    if (a.nlayouts < 1 || a.nlayouts > kMaxLayouts) return (int)hipErrorInvalidValue;
     if (dtype == 2) {
-        if (nv == 1) return run_pass<double, 13, 5, 1>(a, stream);
-        return run_pass<double, 13, 4, 2>(a, stream);
+        if (nv == 1) return run_pass<double, 13, 5, 1, 8, 2>(a, stream);
+        return run_pass<double, 13, 4, 2, 4, 1>(a, stream);
     }
-    if (nv == 1) return run_pass<float, 14, 5, 1>(a, stream);
-    return run_pass<float, 14, 5, 2>(a, stream);
+    if (nv == 1) {
+        if (T == 14) return run_pass<float, 14, 5, 1, 8, 2>(a, stream);
+        return run_pass<float, 13, 5, 1, 8, 4>(a, stream);
+    }
+    return run_pass<float, 13, 4, 2, 4, 1>(a, stream);
+}
+
+int launch_tables(const TableJob* jobs, int njobs, double2* out, void* stream) {
+    for (int s = 0; s < njobs; s += 64) {
+        TableJobs tj;
+        const int cnt = njobs - s < 64 ? njobs - s : 64;
+        for (int i = 0; i < cnt; i++) tj.j[i] = jobs[s + i];
+        hipLaunchKernelGGL(k_tables, dim3(cnt), dim3(256), 0, (hipStream_t)stream, tj, out);
+        const int e = (int)hipGetLastError();
+        if (e) return e;
+    }
+    return 0;
 }
 
 int launch_reduce_slots(const double* partials, uint64_t nrows, int nslots, const int* dst, int accumulate,

@@ -132,7 +132,7 @@ def test_plan_covers_every_qubit_once(sv, dtype, n):
     if dtype == "c128" and n > 33:
         pytest.skip("complex128 holds at most 33 qubits")
     d = sv.describe(n, dtype)
-    for key in ("nv1", "nv2"):
+    for key in ("nv1", "grad_nv1", "grad_nv2"):
         groups = d["plans"][key]
         covered = []
         for gi, g in enumerate(groups):

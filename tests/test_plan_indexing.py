@@ -69,7 +69,7 @@ def replay(n, g, G):
 def test_every_layout_is_a_bijection(sv, dtype, n):
     d = sv.describe(n, dtype)
     G = 3 if dtype == "c128" else 4
-    for key in ("nv1", "nv2"):
+    for key in ("nv1", "grad_nv1", "grad_nv2"):
         for g in d["plans"][key]:
             replay(n, g, G)
 
@@ -81,7 +81,7 @@ def test_large_plans_in_bounds(sv, dtype, n):
     if dtype == "c128" and n > 33:
         pytest.skip("complex128 holds at most 33 qubits")
     d = sv.describe(n, dtype)
-    for key in ("nv1", "nv2"):
+    for key in ("nv1", "grad_nv1", "grad_nv2"):
         for g in d["plans"][key]:
             T, c, lo, gb = g["T"], g["c"], g["lo"], g["g"]
             assert g["ntiles"] == 1 << (n - T)
