@@ -181,7 +181,8 @@ int sv_schedule_second_order(int p, double tau, const double* A, const double* B
  * evaluate |psi> = exp(-i beta_b H_D) exp(-i gamma_a H_C_i) |+>^{n_i} and write
  *   energy_out[(i * n_gamma + a) * n_beta + b] = <H_C_i>
  *   pgs_out   [(i * n_gamma + a) * n_beta + b] = ground-state probability.
- * Instances may differ in n (1..20).  dtype selects the amplitude storage.
+ * Instances may differ in n (1..19 for SV_C64, 1..18 for SV_C128; larger n
+ * returns SV_ERR_UNSUPPORTED).  dtype selects the amplitude storage.
  * Outputs are host arrays.  Runs on the given stream; synchronises. */
 int sv_batch_p1_scan(int n_inst, const sv_ising* insts, int n_gamma, const double* gammas,
                      int n_beta, const double* betas, sv_dtype dtype, void* hip_stream,

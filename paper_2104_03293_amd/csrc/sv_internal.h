@@ -155,7 +155,40 @@ int launch_reduce_slots(const double* partials, uint64_t nrows, int nslots, cons
 int launch_ground(int dtype, const GroundArgs& a, void* stream);
 int launch_ground_finish(const GroundArgs& a, double* out_e, uint64_t* out_cnt,
                          uint64_t* out_arg, void* stream);
-int launch_batch_p1(const void* bargs, void* stream);
+// ---------------------------------------------------------------- batch scan
+// One instance of the p = 1 landscape scan (device array of these).
+struct BatchInst {
+    int32_t n, m;
+    int32_t hoff, coff;     // offsets into the packed fields / couplings
+    uint64_t eoff;          // offset of this instance's energy table
+    double emin, etol;      // ground-state test
+    int32_t lut_lo, lut_n;  // integer energies lie in [lut_lo, lut_lo + lut_n); lut_n = 0: real
+};
+
+struct BatchArgs {
+    const BatchInst* inst;
+    int32_t ninst;
+    const double* h;        // packed fields
+    const int32_t* ei;      // packed couplings (instance-local spin indices)
+    const int32_t* ej;
+    const double* J;
+    double* etab;           // energy tables, Sum 2^n_i entries
+    const int32_t* unit_inst;  // work unit -> instance (units sorted by n, largest first)
+    const int32_t* unit_gam;   // work unit -> gamma index
+    int32_t nunits;
+    const double* gammas;
+    int32_t ng;
+    const double* betas;
+    int32_t nb;
+    double* out_e;          // [inst][gamma][beta]
+    double* out_p;
+    unsigned int* counter;  // work-queue head (zeroed before the launch)
+    void* scratch;          // per-workgroup slices for states larger than LDS
+    uint64_t scratch_elems; // elements per workgroup slot
+};
+
+int launch_batch_energy(const BatchArgs& a, int max_n, void* stream);
+int launch_batch_scan(int dtype, const BatchArgs& a, int grid, void* stream);
 
 // Compile-time tile shapes per (dtype, vectors): T tile bits, R register bits.
 struct Shape {

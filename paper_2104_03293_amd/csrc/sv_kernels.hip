@@ -732,3 +732,262 @@ int launch_ground_finish(const GroundArgs& a, double* out_e, uint64_t* out_cnt, 
 }
 
 }  // namespace svk
+
+// ============================================================================ batch scan
+// p = 1 landscape over many small instances (Sec. III.C.1, Fig. 5): for each
+// instance i and grid point (gamma_a, beta_b), psi = exp(-i beta_b H_D)
+// exp(-i gamma_a H_C) |+>, then <H_C> and the ground-state probability.
+namespace svk {
+
+// Energy tables E_i(z) for every instance (Eq. HC), one thread per basis state.
+__global__ void __launch_bounds__(256) k_batch_energy(const BatchArgs a) {
+    const int i = blockIdx.y;
+    const BatchInst in = a.inst[i];
+    const uint64_t N = 1ull << in.n;
+    for (uint64_t z = (uint64_t)blockIdx.x * 256 + threadIdx.x; z < N; z += (uint64_t)gridDim.x * 256) {
+        double e = 0.0;
+        for (int q = 0; q < in.n; q++) e += a.h[in.hoff + q] * (((z >> q) & 1) ? 1.0 : -1.0);
+        for (int k = 0; k < in.m; k++) {
+            const int u = a.ei[in.coff + k], v = a.ej[in.coff + k];
+            const double su = ((z >> u) & 1) ? 1.0 : -1.0, sv = ((z >> v) & 1) ? 1.0 : -1.0;
+            e += a.J[in.coff + k] * su * sv;
+        }
+        a.etab[in.eoff + z] = e;
+    }
+}
+
+// Minimum of each energy table (one workgroup per instance).
+__global__ void __launch_bounds__(256) k_batch_emin(const BatchArgs a, BatchInst* inst) {
+    __shared__ double sh[256];
+    const int i = blockIdx.x;
+    const BatchInst in = a.inst[i];
+    const uint64_t N = 1ull << in.n;
+    double e = INFINITY;
+    for (uint64_t z = threadIdx.x; z < N; z += 256) e = fmin(e, a.etab[in.eoff + z]);
+    sh[threadIdx.x] = e;
+    __syncthreads();
+    for (int w = 128; w >= 1; w >>= 1) {
+        if ((int)threadIdx.x < w) sh[threadIdx.x] = fmin(sh[threadIdx.x], sh[threadIdx.x + w]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) inst[i].emin = sh[0];
+}
+
+template <typename Real>
+struct BatchCfg {
+    static constexpr int S = sizeof(Real) == 4 ? 14 : 13;  // log2 of the LDS state size
+    static constexpr int G = sizeof(Real) == 4 ? 4 : 3;    // swizzle width
+};
+
+__device__ __forceinline__ uint32_t bswz(uint32_t z, int G) { return lds_swizzle(z, G); }
+
+// exp(-i beta sigma^x) on every qubit of an LDS-resident state of 2^nb elements
+// (bits 0..nb-1), in register blocks of 5 bits.
+template <typename Real>
+__device__ void lds_mixer(typename V2T<Real>::type* st, int nb, Real c, Real s) {
+    using V2 = typename V2T<Real>::type;
+    constexpr int G = BatchCfg<Real>::G;
+    const int nblk = (nb + 4) / 5;
+    uint32_t done = 0;
+    for (int j = 0; j < nblk; j++) {
+        const int a0 = min(5 * j, nb - 5);
+        uint32_t act = 0;
+        for (int k = 0; k < 5; k++)
+            if (!((done >> (a0 + k)) & 1u)) act |= 1u << k;
+        done |= 31u << a0;
+        const uint32_t nq = 1u << (nb - 5);
+        for (uint32_t q = threadIdx.x; q < nq; q += 256) {
+            const uint32_t zb = (q & ((1u << a0) - 1u)) | ((q >> a0) << (a0 + 5));
+            V2 v[32];
+#pragma unroll
+            for (int r = 0; r < 32; r++) v[r] = st[bswz(zb | ((uint32_t)r << a0), G)];
+#pragma unroll
+            for (int k = 0; k < 5; k++) {
+                if (!((act >> k) & 1u)) continue;
+#pragma unroll
+                for (int r = 0; r < 32; r++) {
+                    if (r & (1 << k)) continue;
+                    const int r2 = r | (1 << k);
+                    const Real ar = v[r].x, ai = v[r].y, br = v[r2].x, bi = v[r2].y;
+                    v[r].x = c * ar + s * bi;
+                    v[r].y = c * ai - s * br;
+                    v[r2].x = c * br + s * ai;
+                    v[r2].y = c * bi - s * ar;
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 32; r++) st[bswz(zb | ((uint32_t)r << a0), G)] = v[r];
+        }
+        __syncthreads();
+    }
+}
+
+// Persistent scan: workgroups take (instance, gamma) units from a queue, largest
+// n first, and evaluate every beta of the grid for that unit.
+template <typename Real>
+__global__ void __launch_bounds__(256) k_batch_scan(const BatchArgs a) {
+    using V2 = typename V2T<Real>::type;
+    constexpr int S = BatchCfg<Real>::S;
+    constexpr int G = BatchCfg<Real>::G;
+    __shared__ V2 st[1 << S];
+    __shared__ double2 lut[1024];
+    __shared__ double red[4][3];
+    __shared__ int s_unit;
+    const int t = threadIdx.x;
+    V2* slot = reinterpret_cast<V2*>(a.scratch) + (uint64_t)blockIdx.x * a.scratch_elems;
+
+    for (;;) {
+        if (t == 0) s_unit = (int)atomicAdd(a.counter, 1u);
+        __syncthreads();
+        const int u = s_unit;
+        __syncthreads();
+        if (u >= a.nunits) break;  // every wave of the workgroup sees the same u
+        const BatchInst in = a.inst[a.unit_inst[u]];
+        const double gam = a.gammas[a.unit_gam[u]];
+        const int n = in.n;
+        const double amp0 = exp2(-0.5 * n);
+        const double* E = a.etab + in.eoff;
+        const bool intE = in.lut_n > 0;
+        if (intE) {
+            for (int m = t; m < in.lut_n; m += 256) {
+                double sn, cs;
+                sincos(gam * (double)(in.lut_lo + m), &sn, &cs);
+                lut[m] = make_double2(amp0 * cs, -amp0 * sn);
+            }
+            __syncthreads();
+        }
+        auto phi = [&](uint64_t z) -> V2 {  // amp0 exp(-i gamma E(z))
+            const double e = E[z];
+            double pr, pi;
+            if (intE) {
+                const double2 w = lut[(int)e - in.lut_lo];
+                pr = w.x;
+                pi = w.y;
+            } else {
+                double sn, cs;
+                sincos(gam * e, &sn, &cs);
+                pr = amp0 * cs;
+                pi = -amp0 * sn;
+            }
+            V2 x;
+            x.x = (Real)pr;
+            x.y = (Real)pi;
+            return x;
+        };
+        for (int b = 0; b < a.nb; b++) {
+            const double beta = a.betas[b];
+            const Real c = (Real)cos(beta), s = (Real)sin(beta);
+            double r_e = 0.0, r_p = 0.0;
+            if (n <= S) {
+                const uint32_t N = 1u << n;
+                for (uint32_t z = t; z < N; z += 256) st[bswz(z, G)] = phi(z);
+                __syncthreads();
+                if (n >= 5) {
+                    lds_mixer<Real>(st, n, c, s);
+                } else {
+                    if (t == 0) {  // tiny states: plain pair loops
+                        for (int q = 0; q < n; q++)
+                            for (uint32_t z = 0; z < N; z++) {
+                                if ((z >> q) & 1u) continue;
+                                V2& x = st[bswz(z, G)];
+                                V2& y = st[bswz(z | (1u << q), G)];
+                                const Real ar = x.x, ai = x.y, br = y.x, bi = y.y;
+                                x.x = c * ar + s * bi;
+                                x.y = c * ai - s * br;
+                                y.x = c * br + s * ai;
+                                y.y = c * bi - s * ar;
+                            }
+                    }
+                    __syncthreads();
+                }
+                for (uint32_t z = t; z < N; z += 256) {
+                    const V2 x = st[bswz(z, G)];
+                    const double p2 = (double)x.x * x.x + (double)x.y * x.y;
+                    const double e = E[z];
+                    r_e += e * p2;
+                    if (fabs(e - in.emin) <= in.etol) r_p += p2;
+                }
+            } else {
+                // low S bits slice by slice in LDS, written to this workgroup's slot
+                const int nh = n - S;
+                for (uint32_t sl = 0; sl < (1u << nh); sl++) {
+                    const uint64_t off = (uint64_t)sl << S;
+                    for (uint32_t z = t; z < (1u << S); z += 256) st[bswz(z, G)] = phi(off + z);
+                    __syncthreads();
+                    lds_mixer<Real>(st, S, c, s);
+                    for (uint32_t z = t; z < (1u << S); z += 256) slot[off + z] = st[bswz(z, G)];
+                    __syncthreads();
+                }
+                // high bits: each thread holds the 2^nh amplitudes of one low index
+                for (uint32_t l = t; l < (1u << S); l += 256) {
+                    V2 v[32];
+#pragma unroll
+                    for (int r = 0; r < 32; r++)
+                        if (r < (1 << nh)) v[r] = slot[((uint64_t)r << S) | l];
+#pragma unroll
+                    for (int k = 0; k < 5; k++) {
+                        if (k >= nh) continue;
+#pragma unroll
+                        for (int r = 0; r < 32; r++) {
+                            if ((r & (1 << k)) || r >= (1 << nh)) continue;
+                            const int r2 = r | (1 << k);
+                            const Real ar = v[r].x, ai = v[r].y, br = v[r2].x, bi = v[r2].y;
+                            v[r].x = c * ar + s * bi;
+                            v[r].y = c * ai - s * br;
+                            v[r2].x = c * br + s * ai;
+                            v[r2].y = c * bi - s * ar;
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < 32; r++) {
+                        if (r >= (1 << nh)) continue;
+                        const double p2 = (double)v[r].x * v[r].x + (double)v[r].y * v[r].y;
+                        const double e = E[((uint64_t)r << S) | l];
+                        r_e += e * p2;
+                        if (fabs(e - in.emin) <= in.etol) r_p += p2;
+                    }
+                }
+                __syncthreads();  // slot reads done before the next beta overwrites it
+            }
+            // fixed-order workgroup sum
+#pragma unroll
+            for (int off = 32; off >= 1; off >>= 1) {
+                r_e += __shfl_xor(r_e, off);
+                r_p += __shfl_xor(r_p, off);
+            }
+            if ((t & 63) == 0) {
+                red[t >> 6][0] = r_e;
+                red[t >> 6][1] = r_p;
+            }
+            __syncthreads();
+            if (t == 0) {
+                const double se = red[0][0] + red[1][0] + red[2][0] + red[3][0];
+                const double sp = red[0][1] + red[1][1] + red[2][1] + red[3][1];
+                const uint64_t o = ((uint64_t)a.unit_inst[u] * a.ng + a.unit_gam[u]) * a.nb + b;
+                a.out_e[o] = se;
+                a.out_p[o] = sp;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+int launch_batch_energy(const BatchArgs& a, int max_n, void* stream) {
+    const unsigned gx = (unsigned)std::max(1, std::min(1024, (1 << max_n) / 256));
+    hipLaunchKernelGGL(k_batch_energy, dim3(gx, a.ninst), dim3(256), 0, (hipStream_t)stream, a);
+    int e = (int)hipGetLastError();
+    if (e) return e;
+    hipLaunchKernelGGL(k_batch_emin, dim3(a.ninst), dim3(256), 0, (hipStream_t)stream, a,
+                       const_cast<BatchInst*>(a.inst));
+    return (int)hipGetLastError();
+}
+
+int launch_batch_scan(int dtype, const BatchArgs& a, int grid, void* stream) {
+    if (dtype == 2)
+        hipLaunchKernelGGL(k_batch_scan<double>, dim3(grid), dim3(256), 0, (hipStream_t)stream, a);
+    else
+        hipLaunchKernelGGL(k_batch_scan<float>, dim3(grid), dim3(256), 0, (hipStream_t)stream, a);
+    return (int)hipGetLastError();
+}
+
+}  // namespace svk

@@ -282,3 +282,67 @@ def test_grad_errors(sv):
     c = sv.State(11, "c128")
     with pytest.raises(sv.SVError):
         sv.qaoa_forward(c, H, [0.1], [0.2])
+
+
+# ----------------------------------------------------------------------------- batch scan
+def _batch_oracle(orc, inst, gam, bet):
+    E = orc.energies(inst)
+    gs = orc.ground(inst, E)
+    en = np.empty((len(gam), len(bet)))
+    pg = np.empty((len(gam), len(bet)))
+    for a, g in enumerate(gam):
+        for b, bb in enumerate(bet):
+            psi = orc.qaoa_state(inst, [g], [bb], E=E)
+            _, en[a, b], pg[a, b] = orc.observables(inst, psi, E=E, gs=gs)
+    return en, pg
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_scan_vs_oracle(sv, orc, dtype):
+    """Uneven n (tiny, LDS-resident and larger than one LDS slice), integer and
+    real-valued instances, half-open grid with its gamma = 0 and beta = 0 edges."""
+    ns = [1, 3, 4, 7, 10, 12, 13, 14, 15, 16, 18]
+    insts = []
+    for k, n in enumerate(ns):
+        if n >= 4:
+            insts.append(I.regular3_pm1(n, 500 + k))
+        else:
+            insts.append(instance_for(n, "real", 500 + k))
+    insts.append(I.random_real(11, 20, 77))
+    gam, bet = I.config3_grid(6, 5)
+    Hs = [sv.Ising.from_instance(x) for x in insts]
+    en, pg = sv.batch_p1_scan(Hs, gam, bet, dtype=dtype)
+    for i, inst in enumerate(insts):
+        ren, rpg = _batch_oracle(orc, inst, gam, bet)
+        tol = 1e-6 * max(orc.coeff_scale(inst), 1.0)
+        assert np.max(np.abs(en[i] - ren)) <= tol, (i, inst["n"])
+        assert np.max(np.abs(pg[i] - rpg)) <= PROB_TOL[dtype], (i, inst["n"])
+
+
+def test_batch_scan_closed_form_full_grid(sv, orc):
+    """32 x 32 grid of the batched workload on 64 instances: <H_C> at every point
+    against the depth-one closed form (test_oracle_pins.p1_closed_form_energy)."""
+    from tests.test_oracle_pins import p1_closed_form_energy
+
+    insts = I.config3_instances(64)
+    gam, bet = I.config3_grid()
+    Hs = [sv.Ising.from_instance(x) for x in insts]
+    en, pg = sv.batch_p1_scan(Hs, gam, bet, dtype="c64")
+    for i in range(0, 64, 7):
+        inst = insts[i]
+        for a in (0, 3, 17, 31):
+            for b in (0, 5, 22, 31):
+                ref = p1_closed_form_energy(inst, gam[a], bet[b])
+                assert abs(en[i, a, b] - ref) <= 1e-6 * max(orc.coeff_scale(inst), 1.0)
+    # gamma = 0 or beta = 0: P_gs = degeneracy / 2^n exactly (up to f32 rounding)
+    for i in range(0, 64, 9):
+        _, deg, _ = orc.ground(insts[i])
+        assert abs(pg[i, 0, 7] - deg / 2 ** insts[i]["n"]) <= 1e-6
+        assert abs(pg[i, 5, 0] - deg / 2 ** insts[i]["n"]) <= 1e-6
+
+
+def test_batch_scan_errors(sv):
+    H = sv.Ising.from_instance(I.regular3_pm1(20, 1))
+    with pytest.raises(sv.SVError) as e:
+        sv.batch_p1_scan([H], [0.1], [0.2], dtype="c128")
+    assert e.value.code == 4
