@@ -198,6 +198,12 @@ int sv_tune_set(const char* name, int value);
 int sv_tune_get(const char* name, int* value);
 int sv_tune_describe(int n, sv_dtype dtype, char* buf, size_t len);
 
+/* Per-(dtype, n) knob overrides chosen by the autotuner: a text file of lines
+ * "<c64|c128> <n> <knob> <value>".  Read from $SV_TUNE_CACHE at the first
+ * plan, or (replacing what was loaded) by sv_tune_load(path); path NULL
+ * clears them.  Overrides take precedence over sv_tune_set values. */
+int sv_tune_load(const char* path);
+
 /* ------------------------------------------------------------- profiling --
  * sv_profile_enable(1) clears the record and starts timing every tile-pass
  * launch with a pair of HIP events on the launch stream; (0) stops it.

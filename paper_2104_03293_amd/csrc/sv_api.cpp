@@ -55,7 +55,56 @@ int knob(const char* k) {
     std::lock_guard<std::mutex> g(g_knob_mu);
     return g_knobs[k];
 }
+// Tuned per-(dtype, n) overrides: text lines "c128 32 cmin128 4" (from the
+// autotuner), loaded from $SV_TUNE_CACHE on first use or by sv_tune_load.
+std::map<std::tuple<int, int, std::string>, int> g_tuned;
+bool g_tuned_loaded = false;
+
+int load_tuned_locked(const char* path) {
+    FILE* f = fopen(path, "r");
+    if (!f) return -1;
+    char dt[16], name[64];
+    int n, v;
+    int cnt = 0;
+    while (fscanf(f, "%15s %d %63s %d", dt, &n, name, &v) == 4) {
+        const int d = std::string(dt) == "c128" ? 2 : (std::string(dt) == "c64" ? 1 : 0);
+        if (d && g_knobs.count(name)) {
+            g_tuned[std::make_tuple(d, n, std::string(name))] = v;
+            cnt++;
+        }
+    }
+    fclose(f);
+    return cnt;
+}
+
+// Knob value for a plan: tuned override for (dtype, n) if present, else the global value.
+int knob_for(const char* k, int dtype, int n) {
+    std::lock_guard<std::mutex> g(g_knob_mu);
+    if (!g_tuned_loaded) {
+        g_tuned_loaded = true;
+        const char* p = getenv("SV_TUNE_CACHE");
+        if (p && *p) (void)load_tuned_locked(p);
+    }
+    auto it = g_tuned.find(std::make_tuple(dtype, n, std::string(k)));
+    if (it != g_tuned.end()) return it->second;
+    return g_knobs[k];
+}
 }  // namespace
+
+extern "C" int sv_tune_load(const char* path) {
+    if (!path) {
+        std::lock_guard<std::mutex> g(g_knob_mu);
+        g_tuned.clear();
+        g_tuned_loaded = true;
+        return SV_OK;
+    }
+    std::lock_guard<std::mutex> g(g_knob_mu);
+    g_tuned.clear();
+    g_tuned_loaded = true;
+    const int cnt = load_tuned_locked(path);
+    if (cnt < 0) return fail(SV_ERR_ARG, "sv_tune_load: cannot read '%s'", path);
+    return SV_OK;
+}
 
 extern "C" int sv_tune_set(const char* name, int value) {
     if (!name) return fail(SV_ERR_ARG, "sv_tune_set: name is NULL");
@@ -336,7 +385,7 @@ static std::vector<Geometry> plan_groups(int n, sv_dtype dt, int nv, bool grad =
         return out;
     }
     out.push_back(make_geometry(n, T, R, T, T, 0, G));
-    const int cmin = std::max(G, knob(dt == SV_C128 ? "cmin128" : "cmin64"));
+    const int cmin = std::max(G, knob_for(dt == SV_C128 ? "cmin128" : "cmin64", (int)dt, n));
     const int rest = n - T, gmax = T - cmin;
     const int ng = (rest + gmax - 1) / gmax;
     int lo = T;
@@ -1202,7 +1251,7 @@ extern "C" int sv_qaoa_forward(sv_state s, sv_ising H, int p, const double* gamm
     Plan plan = make_plan(s->n, s->dt);
     std::vector<Event> ev;
     forward_events(ev, (int)plan.by_nv[1].size(), p, gamma, beta, from_plus != 0, -1);
-    Program prog = build_program(ev, 0, knob("fuse") != 0);
+    Program prog = build_program(ev, 0, knob_for("fuse", (int)s->dt, s->n) != 0);
     return run_program(s, nullptr, H, prog, plan, false);
 }
 
@@ -1216,7 +1265,7 @@ extern "C" int sv_aqa_run(sv_state s, sv_ising H, int steps, const double* gamma
     Plan plan = make_plan(s->n, s->dt);
     std::vector<Event> ev;
     forward_events(ev, (int)plan.by_nv[1].size(), steps, gamma, beta, true, want ? 0 : -1);
-    Program prog = build_program(ev, want ? 3 * steps : 0, knob("fuse") != 0);
+    Program prog = build_program(ev, want ? 3 * steps : 0, knob_for("fuse", (int)s->dt, s->n) != 0);
     rc = run_program(s, nullptr, H, prog, plan, want);
     if (rc || !want) return rc;
     rc = fetch_results(s, 3 * steps);
@@ -1284,7 +1333,7 @@ extern "C" int sv_grad(sv_state psi, sv_state lam, sv_ising H, int p, const doub
             ev.push_back(ph);
         }
     }
-    Program prog = build_program(ev, 3 + 2 * p, knob("fuse") != 0);
+    Program prog = build_program(ev, 3 + 2 * p, knob_for("fuse", (int)psi->dt, psi->n) != 0);
     // Trims.  In the pass where lam = E psi is formed, psi is mixed forward by
     // one group and then undone by the same group: the loaded values are already
     // that result, so psi is not written back.  The final pass writes nothing.

@@ -59,6 +59,7 @@ def _load():
         "sv_tune_set": (ip, [ctypes.c_char_p, ip]),
         "sv_tune_get": (ip, [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int)]),
         "sv_tune_describe": (ip, [ip, ip, ctypes.c_char_p, ctypes.c_size_t]),
+        "sv_tune_load": (ip, [ctypes.c_char_p]),
         "sv_profile_enable": (ip, [ip]),
         "sv_profile_report": (ip, [ctypes.c_char_p, ctypes.c_size_t]),
     }
@@ -307,6 +308,10 @@ def tune_get(name: str) -> int:
     v = ctypes.c_int()
     _check(lib.sv_tune_get(name.encode(), ctypes.byref(v)))
     return v.value
+
+
+def tune_load(path=None) -> None:
+    _check(lib.sv_tune_load(None if path is None else str(path).encode()))
 
 
 def describe(n: int, dtype: str = "c128") -> dict:

@@ -158,3 +158,22 @@ def test_plan_covers_every_qubit_once(sv, dtype, n):
             if n >= T and len(g["blocks"]) > 1:
                 assert min(g["blocks"][0]["bits"]) >= 6
         assert sorted(covered) == list(range(n))
+
+
+def test_tune_cache_overrides_plan(sv, tmp_path):
+    """A tuned (dtype, n) override changes the plan for that size only."""
+    base = sv.describe(30, "c128")["plans"]["nv1"]
+    f = tmp_path / "cache.txt"
+    f.write_text("c128 30 cmin128 5\nc64 30 bogus 3\n")
+    sv.tune_load(f)
+    try:
+        tuned = sv.describe(30, "c128")["plans"]["nv1"]
+        other = sv.describe(29, "c128")["plans"]["nv1"]
+    finally:
+        sv.tune_load(None)
+    assert all(g["c"] >= 5 for g in tuned[1:])
+    assert [g["c"] for g in tuned] != [g["c"] for g in base]
+    assert [g["c"] for g in other] == [g["c"] for g in sv.describe(29, "c128")["plans"]["nv1"]]
+    with pytest.raises(sv.SVError):
+        sv.tune_load(tmp_path / "missing.txt")
+    sv.tune_load(None)
