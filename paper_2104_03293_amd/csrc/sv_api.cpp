@@ -853,7 +853,11 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         a.store = p.store;
         a.nslots = (int)p.slot_dst.size();
         a.nops = 0;
-        for (const Op& op : p.ops) a.nops += op.kind != 0;
+        a.need_e = 0;
+        for (const Op& op : p.ops) {
+            a.nops += op.kind != 0;
+            if (op.kind == OP_POINT && H) a.need_e = 1;
+        }
         a.nphase = (int)p.phase.size();
         a.ptab = s->w.d_tab;
         a.lut_half = lut_half;

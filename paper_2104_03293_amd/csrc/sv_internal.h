@@ -125,6 +125,7 @@ struct PassArgs {
     int32_t store;          // bit0 store psi, bit1 store lam
     int32_t nslots;
     int32_t nops;           // informational; ops[i].kind == 0 marks an absent slot
+    int32_t need_e;         // the POINT op evaluates E (tile fields needed)
     int32_t nphase;
     int32_t lut_half;       // L of the integer phase tables, -1 for real-valued instances
     uint32_t qph_off[kMaxPhase];

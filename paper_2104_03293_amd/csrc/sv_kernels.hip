@@ -236,10 +236,8 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
     V2* __restrict__ psi = reinterpret_cast<V2*>(a.psi);
     V2* __restrict__ lam = reinterpret_cast<V2*>(a.lam);
 
-    // ---- prologue: fields seen by the tile bits
-    if (t < 64) tile_fields(a.is, geo, tg, base, T, s_g, &s_ew);
-
-    // ---- load in layout 0
+    // ---- load in layout 0 (issued before the per-tile field computation so
+    // that the field loop overlaps the memory latency)
     int cur = 0;
     const GeoLayout* L = &geo->L[0];
     uint32_t thr_u = thread_index_bits(t, L);
@@ -301,6 +299,8 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
 #pragma unroll
     for (int v = 0; v < NV; v++) pend[v] = 1.0;
 
+    // ---- fields seen by the tile bits (only passes that evaluate E need them)
+    if (a.need_e && t < 64) tile_fields(a.is, geo, tg, base, T, s_g, &s_ew);
     __syncthreads();  // s_g, s_ew ready
 
     // The pass program has a fixed shape: two mixer slots, one point slot, two
