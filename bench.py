@@ -43,6 +43,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip gradient / c64 / CPU-baseline legs")
     ap.add_argument("--cpu-sample-n", type=int, default=28)
     ap.add_argument("--cpu-sample-p", type=int, default=8)
+    ap.add_argument("--knob", action="append", default=[], metavar="NAME=VALUE",
+                    help="set a plan knob of the library before the run (repeatable)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (counter reference)")
     args = ap.parse_args()
@@ -57,6 +59,10 @@ def main():
     from paper_2104_03293_amd import sv
 
     torch.cuda.set_device(0)
+    for kv in args.knob:
+        name, val = kv.split("=")
+        sv.tune_set(name, int(val))
+        log(f"[bench] knob {name}={int(val)}")
     if args.copy_ref_mib > 0:
         nel = args.copy_ref_mib << 18  # float32 elements
         src = torch.ones(nel, dtype=torch.float32, device="cuda")

@@ -50,6 +50,9 @@ std::map<std::string, int> g_knobs = {
     {"fuse", 1},      // 1: snake-ordered fused passes; 0: one op per pass
     {"cmin64", 4},    // minimum carrier bits (contiguous run 2^c amplitudes) for complex64
     {"cmin128", 3},   // ... for complex128
+    {"ntmin", 6},     // passes whose contiguous runs hold >= 2^ntmin amplitudes stream with nontemporal hints
+    {"persist", 0},   // tile passes: workgroups per CU of a persistent grid (0: one workgroup per tile)
+    {"stagger", 0},   // persistent grids: start delay of the second half (units of 64*127 clocks)
 };
 int knob(const char* k) {
     std::lock_guard<std::mutex> g(g_knob_mu);
@@ -114,6 +117,9 @@ extern "C" int sv_tune_set(const char* name, int value) {
     if (std::string(name) == "fuse" && (value < 0 || value > 1)) return fail(SV_ERR_ARG, "fuse must be 0 or 1");
     if ((std::string(name) == "cmin64" || std::string(name) == "cmin128") && (value < 0 || value > 8))
         return fail(SV_ERR_ARG, "%s must be in [0, 8]", name);
+    if (std::string(name) == "ntmin" && (value < 0 || value > 64)) return fail(SV_ERR_ARG, "ntmin must be in [0, 64]");
+    if (std::string(name) == "persist" && (value < 0 || value > 8)) return fail(SV_ERR_ARG, "persist must be in [0, 8]");
+    if (std::string(name) == "stagger" && (value < 0 || value > 64)) return fail(SV_ERR_ARG, "stagger must be in [0, 64]");
     it->second = value;
     return SV_OK;
 }
@@ -230,10 +236,12 @@ struct sv_state_s {
     Work w;
 };
 
+// The amplitude type is part of the key: it sets the LDS swizzle width and
+// the byte strides stored in the table.
 struct GeoKey {
-    int T, R, c, lo, g, n;
+    int T, R, c, lo, g, n, dt;
     bool operator<(const GeoKey& o) const {
-        return std::tie(T, R, c, lo, g, n) < std::tie(o.T, o.R, o.c, o.lo, o.g, o.n);
+        return std::tie(T, R, c, lo, g, n, dt) < std::tie(o.T, o.R, o.c, o.lo, o.g, o.n, o.dt);
     }
 };
 
@@ -257,10 +265,24 @@ struct sv_ising_s {
     double emin = 0.0;
     uint64_t deg = 0, argmin = 0;
     std::map<GeoKey, GeoBuf*> geos;
+    std::map<std::tuple<int, int, int, int, int>, double*> tfs;  // (T, c, lo, g, n) -> per-tile field table
     std::mutex mu;
 };
 
 static size_t elem_size(sv_dtype d) { return d == SV_C128 ? 16 : 8; }
+
+// Compute units of a device (cached per device; 256 on MI355X).
+static int device_cu_count(int dev) {
+    static std::mutex mu;
+    static std::map<int, int> cache;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    cache[dev] = cus;
+    return cus;
+}
 static int max_n(sv_dtype d) { return d == SV_C128 ? 33 : 34; }
 static bool dtype_ok(int d) { return d == SV_C64 || d == SV_C128; }
 
@@ -408,9 +430,11 @@ static int build_geobuf(const Geometry& geo, const sv_ising_s* H, sv_dtype dt, G
     GeoBuf hb;
     memset(&hb, 0, sizeof(hb));
     const int T = geo.T, R = geo.R, G = swz_bits(dt);
+    const int NTB = T - R, NT = 1 << NTB;
+    if (T >= kTF) return fail(SV_ERR_UNSUPPORTED, "internal: tile of %d bits exceeds the field table", T);
     std::vector<int> inv(64, -1);  // global bit -> tile bit
     for (int l = 0; l < kMaxT; l++) {
-        hb.P[l] = (int8_t)(l < T ? global_bit(geo, l) : -1);
+        hb.P[l] = l < T ? global_bit(geo, l) : -1;
         if (l < T && hb.P[l] >= 0) inv[hb.P[l]] = l;
     }
     auto gmap = [&](uint32_t u) -> uint64_t {
@@ -418,18 +442,23 @@ static int build_geobuf(const Geometry& geo, const sv_ising_s* H, sv_dtype dt, G
     };
     const int K = (int)geo.blocks.size();
     if (K > kMaxLayouts) return fail(SV_ERR_UNSUPPORTED, "internal: too many layouts (%d)", K);
+    // per-thread coupling tables follow the header (instance geometries only)
+    const size_t head = (sizeof(GeoBuf) + 7) / 8;  // in doubles
+    const size_t per_layout = (size_t)(R + 1) * NT;
+    std::vector<double> tabs(H ? (size_t)K * per_layout : 0, 0.0);
     for (int j = 0; j < K; j++) {
         GeoLayout& L = hb.L[j];
         const std::vector<int>& rb = geo.blocks[j];
         uint32_t rmask = 0;
+        L.rbpack = 0;
         for (int k = 0; k < R; k++) {
-            L.rb[k] = (int8_t)rb[k];
             rmask |= 1u << rb[k];
+            L.rbpack |= (uint32_t)rb[k] << (4 * k);
         }
-        int nt = 0;
+        L.tmask = ((1u << T) - 1u) & ~rmask;
+        std::vector<int> tb;  // thread-id bit j -> tile bit tb[j]
         for (int l = 0; l < T; l++)
-            if (!(rmask >> l & 1u)) L.tb[nt++] = (int8_t)l;
-        L.ntb = nt;
+            if (L.tmask >> l & 1u) tb.push_back(l);
         L.act_fwd = (int32_t)geo.act_fwd[j];
         L.act_bwd = (int32_t)geo.act_bwd[j];
         for (int r = 0; r < (1 << R); r++) {
@@ -437,23 +466,27 @@ static int build_geobuf(const Geometry& geo, const sv_ising_s* H, sv_dtype dt, G
             for (int k = 0; k < R; k++)
                 if (r >> k & 1) u |= 1u << rb[k];
             L.reg_u[r] = u;
-            L.reg_lds[r] = swizzle(u & ((1u << (T - 1)) - 1u), G);
+            L.reg_lds[r] = swizzle(u & ((1u << (T - 1)) - 1u), G) * (uint32_t)elem_size(dt);
             L.reg_goff[r] = (u & geo.phantom) ? 0 : gmap(u);
         }
+        L.thr_off = 0;
         if (H) {
+            L.thr_off = (uint32_t)(head + (size_t)j * per_layout);
+            double* tab = tabs.data() + (size_t)j * per_layout;
             std::vector<int> slot_of(T, -1);
             for (int k = 0; k < R; k++) slot_of[rb[k]] = k;
+            auto spin_t = [&](int t, int l) {  // spin of tile bit l (a thread bit) for thread t
+                for (int q = 0; q < NTB; q++)
+                    if (tb[q] == l) return ((t >> q) & 1) ? 1.0 : -1.0;
+                return 0.0;
+            };
             for (int e = 0; e < H->m; e++) {
                 const int la = inv[H->ei[e]], lb = inv[H->ej[e]];
                 if (la < 0 || lb < 0) continue;  // not an intra-tile coupling
                 const double Jv = H->J[e];
                 const int ka = slot_of[la], kb = slot_of[lb];
                 if (ka < 0 && kb < 0) {
-                    if (L.n_tt >= kMaxTT) return fail(SV_ERR_UNSUPPORTED, "internal: too many tile couplings");
-                    L.tt_a[L.n_tt] = (int8_t)la;
-                    L.tt_b[L.n_tt] = (int8_t)lb;
-                    L.tt_J[L.n_tt] = Jv;
-                    L.n_tt++;
+                    for (int t = 0; t < NT; t++) tab[t] += Jv * spin_t(t, la) * spin_t(t, lb);
                 } else if (ka >= 0 && kb >= 0) {
                     for (int r = 0; r < (1 << R); r++) {
                         const double sa = (r >> ka & 1) ? 1.0 : -1.0, sb = (r >> kb & 1) ? 1.0 : -1.0;
@@ -462,17 +495,18 @@ static int build_geobuf(const Geometry& geo, const sv_ising_s* H, sv_dtype dt, G
                 } else {
                     const int k = ka >= 0 ? ka : kb;
                     const int lt = ka >= 0 ? lb : la;
-                    if (L.n_tr[k] >= kMaxTR) return fail(SV_ERR_UNSUPPORTED, "internal: too many couplings");
-                    L.tr_l[k][L.n_tr[k]] = (int8_t)lt;
-                    L.tr_J[k][L.n_tr[k]] = Jv;
-                    L.n_tr[k]++;
+                    for (int t = 0; t < NT; t++) tab[(size_t)(1 + k) * NT + t] += Jv * spin_t(t, lt);
                 }
             }
         }
     }
+    const size_t bytes = head * 8 + tabs.size() * 8;
+    std::vector<double> img(bytes / 8, 0.0);
+    memcpy(img.data(), &hb, sizeof(GeoBuf));
+    if (!tabs.empty()) memcpy(img.data() + head, tabs.data(), tabs.size() * 8);
     GeoBuf* d = nullptr;
-    HIPCHECK(hipMalloc(&d, sizeof(GeoBuf)));
-    hipError_t e = hipMemcpy(d, &hb, sizeof(GeoBuf), hipMemcpyHostToDevice);
+    HIPCHECK(hipMalloc(&d, bytes));
+    hipError_t e = hipMemcpy(d, img.data(), bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(d);
         return fail(SV_ERR_HIP, "hipMemcpy(geo) failed: %s", hipGetErrorString(e));
@@ -485,7 +519,7 @@ static std::mutex g_geo_mu;
 static std::map<GeoKey, GeoBuf*> g_plain_geos;  // instance-free tables (mixer-only passes)
 
 static int get_geobuf(const Geometry& geo, sv_ising_s* H, sv_dtype dt, GeoBuf** out) {
-    GeoKey key{geo.T, geo.R, geo.c, geo.lo, geo.g, geo.n};
+    GeoKey key{geo.T, geo.R, geo.c, geo.lo, geo.g, geo.n, (int)dt};
     if (H) {
         std::lock_guard<std::mutex> g(H->mu);
         auto it = H->geos.find(key);
@@ -747,6 +781,40 @@ static IsingDev ising_dev(const sv_ising_s* H) {
     return d;
 }
 
+// Per-tile field table of an instance for a tile geometry, built once (on the
+// caller's stream, which is synchronized so that later passes on any stream
+// may use it) and kept until the instance is freed.
+static int get_tf(sv_ising_s* H, const Geometry& geo, const GeoBuf* gb, hipStream_t stream, const double** out) {
+    const auto key = std::make_tuple(geo.T, geo.c, geo.lo, geo.g, geo.n);
+    std::lock_guard<std::mutex> g(H->mu);
+    auto it = H->tfs.find(key);
+    if (it != H->tfs.end()) {
+        *out = it->second;
+        return SV_OK;
+    }
+    double* d = nullptr;
+    HIPCHECK(hipMalloc(&d, geo.ntiles * (size_t)kTF * sizeof(double)));
+    TfArgs a;
+    memset(&a, 0, sizeof(a));
+    a.is = ising_dev(H);
+    a.geo = gb;
+    a.tf = d;
+    a.ntiles = geo.ntiles;
+    a.T = geo.T;
+    a.c = geo.c;
+    a.lo = geo.lo;
+    a.g = geo.g;
+    int e = launch_tile_fields(a, stream);
+    if (e == 0) e = (int)hipStreamSynchronize(stream);
+    if (e != 0) {
+        (void)hipFree(d);
+        return fail(SV_ERR_HIP, "field table build failed: %s", hipGetErrorString((hipError_t)e));
+    }
+    H->tfs[key] = d;
+    *out = d;
+    return SV_OK;
+}
+
 static double ground_tol(const sv_ising_s* H) { return H->integer ? 0.0 : 1e-9 * std::max(1.0, H->scale); }
 
 static int run_ground(sv_ising_s* H, hipStream_t stream);
@@ -828,6 +896,10 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
             return fail(SV_ERR_HIP, "table launch failed: %s", hipGetErrorString((hipError_t)e));
         }
     }
+    const int ntmin = knob_for("ntmin", (int)s->dt, s->n);
+    const int persist = knob_for("persist", (int)s->dt, s->n);
+    const int stagger = knob_for("stagger", (int)s->dt, s->n);
+    const int ncu = persist > 0 ? device_cu_count(s->device) : 0;
     for (size_t pi = 0; pi < prog.passes.size(); pi++) {
         const Pass& p = prog.passes[pi];
         const Geometry& geo = plan.by_nv[p.nv][p.group];
@@ -841,7 +913,6 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         a.lam = lam ? lam->ptr : nullptr;
         a.partials = s->w.d_part;
         a.geo = gb;
-        a.is = ising_dev(H);
         a.ntiles = geo.ntiles;
         a.n = s->n;
         a.c = geo.c;
@@ -854,9 +925,17 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         a.nslots = (int)p.slot_dst.size();
         a.nops = 0;
         a.need_e = 0;
+        a.nt = (geo.phantom == 0 && geo.c >= ntmin) ? 3 : 0;
+        a.grid = persist * ncu;
+        a.stagger = stagger;
         for (const Op& op : p.ops) {
             a.nops += op.kind != 0;
             if (op.kind == OP_POINT && H) a.need_e = 1;
+        }
+        a.tf = nullptr;
+        if (a.need_e) {
+            rc = get_tf(H, geo, gb, s->stream, &a.tf);
+            if (rc) return rc;
         }
         a.nphase = (int)p.phase.size();
         a.ptab = s->w.d_tab;
@@ -1090,6 +1169,7 @@ extern "C" int sv_ising_free(sv_ising H) {
                     (void*)H->d_ej, (void*)H->d_J})
         if (p) (void)hipFree(p);
     for (auto& kv : H->geos) (void)hipFree(kv.second);
+    for (auto& kv : H->tfs) (void)hipFree(kv.second);
     delete H;
     return SV_OK;
 }
@@ -1107,6 +1187,9 @@ static int run_ground(sv_ising_s* H, hipStream_t stream) {
     GeoBuf* gb = nullptr;
     int rc = get_geobuf(geo, H, dt, &gb);
     if (rc) return rc;
+    const double* tf = nullptr;
+    rc = get_tf(H, geo, gb, stream, &tf);
+    if (rc) return rc;
     (void)sh;
     double* d_e = nullptr;
     uint64_t *d_c = nullptr, *d_a = nullptr;
@@ -1119,7 +1202,7 @@ static int run_ground(sv_ising_s* H, hipStream_t stream) {
     GroundArgs a;
     memset(&a, 0, sizeof(a));
     a.geo = gb;
-    a.is = ising_dev(H);
+    a.tf = tf;
     a.ntiles = geo.ntiles;
     a.n = H->n;
     a.c = geo.c;
@@ -1507,14 +1590,9 @@ extern "C" int sv_batch_p1_scan(int n_inst, const sv_ising* insts, int n_gamma, 
         }
     const int S = dtype == SV_C64 ? 14 : 13;
     const size_t elem = elem_size(dtype);
-    int dev_cus = 256;
-    {
-        int dev = 0;
-        hipDeviceProp_t prop;
-        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
-            dev_cus = prop.multiProcessorCount;
-    }
-    const int grid = dev_cus;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    const int grid = device_cu_count(dev);
     const uint64_t slot = max_n > S ? (1ull << max_n) : 0;
     const size_t nout = (size_t)n_inst * n_gamma * n_beta;
     hipStream_t st = (hipStream_t)stream;

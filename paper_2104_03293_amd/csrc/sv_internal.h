@@ -61,30 +61,36 @@ struct Op {
     double b;       // MIX: +-cos(beta')
 };
 
-// One layout of one tile geometry (device resident, read with uniform loads).
+// One layout of one tile geometry (device resident, read with uniform loads;
+// everything a kernel reads per layout is a dword or wider, so it comes
+// through the scalar cache without dependent per-byte vector loads).
 struct GeoLayout {
     uint32_t reg_u[64];     // tile-local index of register r (thread part zero)
-    uint32_t reg_lds[64];   // swizzled LDS element index of reg_u[r] without the pivot bit
+    uint32_t reg_lds[64];   // LDS byte offset (swizzled element index x element size) of reg_u[r] without the pivot bit
     uint64_t reg_goff[64];  // global element offset of reg_u[r]
-    int32_t ntb;            // number of thread bits (T - R)
+    uint32_t tmask;         // tile bits held by the thread index: thread-id bit j -> j-th set bit of tmask
+    uint32_t rbpack;        // register slot k -> tile bit (rbpack >> 4k) & 15
+    uint32_t thr_off;       // per-thread coupling table: offset in doubles from the GeoBuf start (0: none)
     int32_t act_fwd;        // register slots butterflied when entering forward
     int32_t act_bwd;        // ... when walking the layouts backwards
-    int32_t n_tt;           // intra-tile couplings with both ends thread bits
-    int8_t tb[kMaxT];       // thread bits, ascending (thread-id bit j -> tile bit tb[j])
-    int8_t rb[8];           // register bits (register-index bit k -> tile bit rb[k])
-    int32_t n_tr[8];        // per register slot: couplings to thread bits
+    int32_t pad;
     double Q[64];           // sum of couplings among register bits, per register r
-    int8_t tt_a[kMaxTT];
-    int8_t tt_b[kMaxTT];
-    double tt_J[kMaxTT];
-    int8_t tr_l[8][kMaxTR];
-    double tr_J[8][kMaxTR];
 };
 
+// Tile geometry table.  Instance geometries append, per layout, a per-thread
+// coupling table of (R + 1) rows of 2^(T-R) doubles (thread t = column t):
+//   row 0      sum over couplings between two thread bits of J s_a s_b
+//   row 1 + k  sum over couplings between register slot k's bit and a thread bit l of J s_l
 struct GeoBuf {
-    int8_t P[kMaxT];  // tile bit -> global bit, -1 = phantom
+    int32_t P[kMaxT];  // tile bit -> global bit, -1 = phantom
     GeoLayout L[kMaxLayouts];
 };
+
+// Per-tile field table of an instance and a tile geometry: kTF doubles per
+// tile, entry l < T = g_l (field seen by tile bit l from h and the couplings
+// to bits outside the tile), entry kTF - 1 = E_fixed (fields and couplings
+// among the bits outside the tile).  Requires T < kTF.
+constexpr int kTF = 16;
 
 // Device copy of an Ising instance.
 struct IsingDev {
@@ -116,7 +122,7 @@ struct PassArgs {
     double* partials;       // [ntiles][nslots]
     const double2* ptab;    // phase tables (k_tables output)
     const GeoBuf* geo;
-    IsingDev is;
+    const double* tf;       // per-tile field table (passes that evaluate E)
     uint64_t ntiles;
     int32_t n, c, lo, g;    // tile geometry
     uint32_t phantom;       // tile-local phantom bits
@@ -126,6 +132,9 @@ struct PassArgs {
     int32_t nslots;
     int32_t nops;           // informational; ops[i].kind == 0 marks an absent slot
     int32_t need_e;         // the POINT op evaluates E (tile fields needed)
+    int32_t nt;             // 3: nontemporal loads and stores (long contiguous runs), 0: plain
+    int32_t grid;           // workgroups launched (< ntiles: persistent grid-stride walk), 0: one per tile
+    int32_t stagger;        // persistent grids: start delay of the second half, in units of s_sleep(127)
     int32_t nphase;
     int32_t lut_half;       // L of the integer phase tables, -1 for real-valued instances
     uint32_t qph_off[kMaxPhase];
@@ -137,7 +146,7 @@ struct PassArgs {
 
 struct GroundArgs {
     const GeoBuf* geo;
-    IsingDev is;
+    const double* tf;       // per-tile field table of the geometry
     uint64_t ntiles;
     int32_t n, c, lo, g;
     uint32_t phantom;
@@ -148,8 +157,18 @@ struct GroundArgs {
     uint64_t* part_arg;     // [ntiles]    mode 1
 };
 
+// Build job of a per-tile field table.
+struct TfArgs {
+    IsingDev is;
+    const GeoBuf* geo;      // any table of the geometry (uses P only)
+    double* tf;             // [ntiles][kTF]
+    uint64_t ntiles;
+    int32_t T, c, lo, g;
+};
+
 // Launchers (sv_kernels.hip).  Return hipError_t as int.
 int launch_pass(int dtype, int nv, int T, const PassArgs& a, void* stream);
+int launch_tile_fields(const TfArgs& a, void* stream);
 int launch_tables(const TableJob* jobs, int njobs, double2* out, void* stream);
 int launch_reduce_slots(const double* partials, uint64_t nrows, int nslots, const int* dst,
                         int accumulate, double* out, void* stream);

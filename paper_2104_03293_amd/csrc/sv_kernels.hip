@@ -40,13 +40,44 @@ __device__ __forceinline__ uint32_t lds_swizzle(uint32_t u, int G) {
     return u ^ (f & ((1u << G) - 1u));
 }
 
+// Streaming (nontemporal) accesses of one complex amplitude.
+typedef double nd2 __attribute__((ext_vector_type(2)));
+typedef float nf2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_nt(const double2* p) {
+    const nd2 v = __builtin_nontemporal_load(reinterpret_cast<const nd2*>(p));
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ float2 ld_nt(const float2* p) {
+    const nf2 v = __builtin_nontemporal_load(reinterpret_cast<const nf2*>(p));
+    return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void st_nt(double2* p, double2 x) {
+    nd2 v;
+    v.x = x.x;
+    v.y = x.y;
+    __builtin_nontemporal_store(v, reinterpret_cast<nd2*>(p));
+}
+__device__ __forceinline__ void st_nt(float2* p, float2 x) {
+    nf2 v;
+    v.x = x.x;
+    v.y = x.y;
+    __builtin_nontemporal_store(v, reinterpret_cast<nf2*>(p));
+}
+
 __device__ __forceinline__ double spin_u(uint32_t u, int l) { return ((u >> l) & 1u) ? 1.0 : -1.0; }
 __device__ __forceinline__ double spin_z(uint64_t z, int i) { return ((z >> i) & 1ull) ? 1.0 : -1.0; }
 
-__device__ __forceinline__ uint32_t thread_index_bits(uint32_t t, const GeoLayout* L) {
-    uint32_t u = 0;
-    const int nt = L->ntb;
-    for (int j = 0; j < nt; j++) u |= ((t >> j) & 1u) << L->tb[j];
+// Tile-local index of the thread part: thread-id bit j goes to the j-th set
+// bit of the layout's (wave-uniform) thread mask.  No memory access.
+template <int NTB>
+__device__ __forceinline__ uint32_t thread_index_bits(uint32_t t, uint32_t tmask) {
+    uint32_t u = 0, m = tmask;
+#pragma unroll
+    for (int j = 0; j < NTB; j++) {
+        const uint32_t l = (uint32_t)__builtin_ctz(m);
+        m &= m - 1u;
+        u |= ((t >> j) & 1u) << l;
+    }
     return u;
 }
 
@@ -62,17 +93,13 @@ struct TileGeom {
     }
 };
 
-// Per-workgroup part of E(z): E_fixed (fields and couplings among bits outside
-// the tile) and g_l = h_{P[l]} + sum of couplings from tile bit l to fixed bits.
-// Wave 0 only; deterministic order.
-__device__ void tile_fields(const IsingDev& is, const GeoBuf* geo, const TileGeom& tg, uint64_t base,
-                            int T, double* s_g, double* s_ew) {
-    const int lane = threadIdx.x;
-    if (is.h == nullptr) {  // mixer-only passes carry no instance
-        if (lane == 0) *s_ew = 0.0;
-        if (lane < T) s_g[lane] = 0.0;
-        return;
-    }
+// Per-tile part of E(z) for one tile (one wave): E_fixed (fields and couplings
+// among the bits outside the tile) and g_l = h_{P[l]} + sum of couplings from
+// tile bit l to the fixed bits, written to the tile's row of the field table.
+// Deterministic order.
+__device__ void tile_fields_row(const IsingDev& is, const GeoBuf* geo, const TileGeom& tg, uint64_t base, int T,
+                                double* __restrict__ row) {
+    const int lane = threadIdx.x & 63;
     double part = 0.0;
     for (int i = lane; i < is.n; i += 64)
         if (!tg.in_tile(i)) part += is.h[i] * spin_z(base, i);
@@ -82,9 +109,9 @@ __device__ void tile_fields(const IsingDev& is, const GeoBuf* geo, const TileGeo
     }
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) part += __shfl_xor(part, off);
-    if (lane == 0) *s_ew = part;
-    if (lane < T) {
-        const int P = geo->P[lane];
+    if (lane == kTF - 1) row[lane] = part;
+    if (lane < kTF - 1) {
+        const int P = lane < T ? geo->P[lane] : -1;
         double gv = 0.0;
         if (P >= 0) {
             gv = is.h[P];
@@ -93,28 +120,44 @@ __device__ void tile_fields(const IsingDev& is, const GeoBuf* geo, const TileGeo
                 if (!tg.in_tile(j)) gv += is.adj_J[q] * spin_z(base, j);
             }
         }
-        s_g[lane] = gv;
+        row[lane] = gv;
     }
+}
+
+// Field table of an instance for one tile geometry, one wave per tile.
+__global__ void __launch_bounds__(256) k_tile_fields(const TfArgs a) {
+    const TileGeom tg{a.c, a.lo, a.g};
+    const uint64_t stride = (uint64_t)gridDim.x * 4;
+    for (uint64_t w = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6); w < a.ntiles; w += stride)
+        tile_fields_row(a.is, a.geo, tg, tg.base(w), a.T, a.tf + w * kTF);
 }
 
 // Thread part of E for layout L: returns e0 = E at register index 0 and the
 // register-bit fields f[k], so that E(r) = e0 + sum_{k: r_k = 1} 2 f[k] + Q[r].
-template <int R>
-__device__ __forceinline__ double thread_energy(const GeoLayout* L, uint32_t thr_u, const double* s_g,
-                                                double ew, double (&f)[R]) {
-    double eth = ew;
-    const int nt = L->ntb;
-    for (int j = 0; j < nt; j++) {
-        const int l = L->tb[j];
-        eth += s_g[l] * spin_u(thr_u, l);
+// s_g holds the tile's g_l (l < T) and E_fixed (entry kTF - 1).  The couplings
+// inside the tile that involve thread bits come from the layout's per-thread
+// table (one coalesced load per row).
+template <int R, int NTB>
+__device__ __forceinline__ double thread_energy(const GeoLayout* L, const GeoBuf* geo, uint32_t t,
+                                                const double* s_g, double (&f)[R]) {
+    constexpr int NT = 1 << NTB;
+    const uint32_t off = L->thr_off;
+    const double* __restrict__ tab = reinterpret_cast<const double*>(geo) + off + t;
+    double eth = s_g[kTF - 1];
+    uint32_t m = L->tmask;
+#pragma unroll
+    for (int j = 0; j < NTB; j++) {
+        const int l = __builtin_ctz(m);
+        m &= m - 1u;
+        const double gl = s_g[l];
+        eth += ((t >> j) & 1u) ? gl : -gl;
     }
-    const int ntt = L->n_tt;
-    for (int q = 0; q < ntt; q++) eth += L->tt_J[q] * spin_u(thr_u, L->tt_a[q]) * spin_u(thr_u, L->tt_b[q]);
+    if (off != 0) eth += tab[0];
+    const uint32_t rbp = L->rbpack;
 #pragma unroll
     for (int k = 0; k < R; k++) {
-        double fv = s_g[L->rb[k]];
-        const int ntr = L->n_tr[k];
-        for (int q = 0; q < ntr; q++) fv += L->tr_J[k][q] * spin_u(thr_u, L->tr_l[k][q]);
+        double fv = s_g[(rbp >> (4 * k)) & 15u];
+        if (off != 0) fv += tab[(1 + k) * NT];
         f[k] = fv;
         eth -= fv;
     }
@@ -214,7 +257,8 @@ __global__ void __launch_bounds__(256) k_tables(const TableJobs jobs, double2* _
 // KC > 0: the pass geometry has exactly KC layouts (compile time, straight-line
 // layout walks); KC == 0: generic kernel with a runtime layout count (used for
 // states smaller than one tile and for real-valued instances).
-template <typename Real, int T, int R, int NV, int NS, int MINB, bool PH, bool INTE, int KC>
+template <typename Real, int T, int R, int NV, int NS, int MINB, bool PH, bool INTE, int KC, int NTM = 0,
+          bool PERSIST = false>
 __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
     using V2 = typename V2T<Real>::type;
     constexpr int NT = 1 << (T - R);
@@ -224,279 +268,317 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
     constexpr int G = (sizeof(Real) == 8) ? 3 : 4;
 
     __shared__ V2 xbuf[1 << (T - 1)];
-    __shared__ double s_g[kMaxT];
-    __shared__ double s_ew;
+    __shared__ double s_g[kTF];  // tile fields g_l and E_fixed (entry kTF - 1)
     __shared__ double s_red[NW][NS];
 
     const uint32_t t = threadIdx.x;
-    const uint64_t tile = blockIdx.x;
     const GeoBuf* __restrict__ geo = a.geo;
     const TileGeom tg{a.c, a.lo, a.g};
-    const uint64_t base = tg.base(tile);
     V2* __restrict__ psi = reinterpret_cast<V2*>(a.psi);
     V2* __restrict__ lam = reinterpret_cast<V2*>(a.lam);
 
-    // ---- load in layout 0 (issued before the per-tile field computation so
-    // that the field loop overlaps the memory latency)
-    int cur = 0;
-    const GeoLayout* L = &geo->L[0];
-    uint32_t thr_u = thread_index_bits(t, L);
-    uint64_t thr_goff = tg.gmap(thr_u);
+    // Persistent launches (fewer workgroups than tiles) walk the tiles with a
+    // grid stride; the second half of such a grid may start late, so that the
+    // workgroups sharing a CU alternate between streaming and arithmetic
+    // instead of loading and computing in lockstep.
+    if (PERSIST && a.stagger > 0 && blockIdx.x >= gridDim.x / 2) {
+        for (int i = 0; i < a.stagger; i++) __builtin_amdgcn_s_sleep(127);
+    }
+    uint64_t tile = blockIdx.x;
+    do {
+        const uint64_t base = tg.base(tile);
 
-    Real vr[NV][NR], vi[NV][NR];
-    // Phantom bits exist only for states smaller than one tile (PH); full tiles
-    // load without per-register tests.
-    if (a.load & 4) {
+        // ---- load in layout 0 (issued before the per-tile field computation so
+        // that the field loop overlaps the memory latency)
+        int cur = 0;
+        const GeoLayout* L = &geo->L[0];
+        uint32_t thr_u = thread_index_bits<T - R>(t, L->tmask);
+        uint64_t thr_goff = tg.gmap(thr_u);
+
+        Real vr[NV][NR], vi[NV][NR];
+        // Phantom bits exist only for states smaller than one tile (PH); full tiles
+        // load without per-register tests.
+        if (a.load & 4) {
 #pragma unroll
-        for (int r = 0; r < NR; r++) {
-            bool valid = true;
-            if constexpr (PH) valid = ((thr_u | L->reg_u[r]) & a.phantom) == 0u;
-            vr[0][r] = valid ? (Real)a.amp0 : (Real)0;
-            vi[0][r] = 0;
+            for (int r = 0; r < NR; r++) {
+                bool valid = true;
+                if constexpr (PH) valid = ((thr_u | L->reg_u[r]) & a.phantom) == 0u;
+                vr[0][r] = valid ? (Real)a.amp0 : (Real)0;
+                vi[0][r] = 0;
+            }
+        } else if (a.load & 1) {
+            const V2* __restrict__ src = psi + (base | thr_goff);
+            if (NTM & 1) {
+#pragma unroll
+                for (int r = 0; r < NR; r++) {
+                    const V2 v = ld_nt(src + L->reg_goff[r]);
+                    vr[0][r] = v.x;
+                    vi[0][r] = v.y;
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < NR; r++) {
+                    V2 v;
+                    if constexpr (PH) {
+                        v.x = 0;
+                        v.y = 0;
+                        if (((thr_u | L->reg_u[r]) & a.phantom) == 0u) v = src[L->reg_goff[r]];
+                    } else {
+                        v = src[L->reg_goff[r]];
+                    }
+                    vr[0][r] = v.x;
+                    vi[0][r] = v.y;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                vr[0][r] = 0;
+                vi[0][r] = 0;
+            }
         }
-    } else if (a.load & 1) {
-        const V2* __restrict__ src = psi + (base | thr_goff);
+        if constexpr (NV == 2) {
+            const V2* __restrict__ src = lam + (base | thr_goff);
 #pragma unroll
-        for (int r = 0; r < NR; r++) {
-            V2 v;
-            if constexpr (PH) {
+            for (int r = 0; r < NR; r++) {
+                V2 v;
                 v.x = 0;
                 v.y = 0;
-                if (((thr_u | L->reg_u[r]) & a.phantom) == 0u) v = src[L->reg_goff[r]];
-            } else {
-                v = src[L->reg_goff[r]];
+                bool ok = (a.load & 2) != 0;
+                if constexpr (PH) ok = ok && ((thr_u | L->reg_u[r]) & a.phantom) == 0u;
+                if (ok) v = src[L->reg_goff[r]];
+                vr[1][r] = v.x;
+                vi[1][r] = v.y;
             }
-            vr[0][r] = v.x;
-            vi[0][r] = v.y;
         }
-    } else {
+
+        if ((t & 63) == 0) {
 #pragma unroll
-        for (int r = 0; r < NR; r++) {
-            vr[0][r] = 0;
-            vi[0][r] = 0;
+            for (int q = 0; q < NS; q++) s_red[t >> 6][q] = 0.0;
         }
-    }
-    if constexpr (NV == 2) {
-        const V2* __restrict__ src = lam + (base | thr_goff);
+        double pend[NV];  // uniform scale every register of vector v still has to be multiplied by
 #pragma unroll
-        for (int r = 0; r < NR; r++) {
-            V2 v;
-            v.x = 0;
-            v.y = 0;
-            bool ok = (a.load & 2) != 0;
-            if constexpr (PH) ok = ok && ((thr_u | L->reg_u[r]) & a.phantom) == 0u;
-            if (ok) v = src[L->reg_goff[r]];
-            vr[1][r] = v.x;
-            vi[1][r] = v.y;
-        }
-    }
+        for (int v = 0; v < NV; v++) pend[v] = 1.0;
 
-    if ((t & 63) == 0) {
-#pragma unroll
-        for (int q = 0; q < NS; q++) s_red[t >> 6][q] = 0.0;
-    }
-    double pend[NV];  // uniform scale every register of vector v still has to be multiplied by
-#pragma unroll
-    for (int v = 0; v < NV; v++) pend[v] = 1.0;
+        // ---- fields seen by the tile bits (only passes that evaluate E need them)
+        if (a.need_e && t < kTF) s_g[t] = a.tf[tile * kTF + t];
+        __syncthreads();  // s_g ready
 
-    // ---- fields seen by the tile bits (only passes that evaluate E need them)
-    if (a.need_e && t < 64) tile_fields(a.is, geo, tg, base, T, s_g, &s_ew);
-    __syncthreads();  // s_g, s_ew ready
-
-    // The pass program has a fixed shape: two mixer slots, one point slot, two
-    // mixer slots (absent slots have kind 0).  A compile-time shape keeps the
-    // amplitude registers in place across ops.
-    constexpr int SLOT_KIND[kMaxOps] = {OP_MIX, OP_MIX, OP_POINT, OP_MIX, OP_MIX};
+        // The pass program has a fixed shape: two mixer slots, one point slot, two
+        // mixer slots (absent slots have kind 0).  A compile-time shape keeps the
+        // amplitude registers in place across ops.
+        constexpr int SLOT_KIND[kMaxOps] = {OP_MIX, OP_MIX, OP_POINT, OP_MIX, OP_MIX};
 #pragma unroll
-    for (int oi = 0; oi < kMaxOps; oi++) {
-        const Op op = a.ops[oi];
-        if (op.kind == 0) continue;
-        if (SLOT_KIND[oi] == OP_MIX) {
-            const int K = KC > 0 ? KC : a.nlayouts;
-            const bool fwd = (cur == 0);
-            double gsum = 0.0;
-            auto round = [&](int step) {
-                const int j = fwd ? step : (K - 1 - step);
-                if (step > 0) {
-                    // LDS exchange cur -> j in two halves (pivot register slot R-1)
-                    const GeoLayout* Lt = &geo->L[j];
-                    const uint32_t new_u = thread_index_bits(t, Lt);
-                    const uint32_t src = lds_swizzle(thr_u, G);
-                    const uint32_t dst = lds_swizzle(new_u, G);
+        for (int oi = 0; oi < kMaxOps; oi++) {
+            const Op op = a.ops[oi];
+            if (op.kind == 0) continue;
+            if (SLOT_KIND[oi] == OP_MIX) {
+                const int K = KC > 0 ? KC : a.nlayouts;
+                const bool fwd = (cur == 0);
+                double gsum = 0.0;
+                auto round = [&](int step) {
+                    const int j = fwd ? step : (K - 1 - step);
+                    if (step > 0) {
+                        // LDS exchange cur -> j in two halves (pivot register slot R-1)
+                        const GeoLayout* Lt = &geo->L[j];
+                        const uint32_t new_u = thread_index_bits<T - R>(t, Lt->tmask);
+                        // byte offsets: one XOR with the table entry per access
+                        const uint32_t src = lds_swizzle(thr_u, G) * (uint32_t)sizeof(V2);
+                        const uint32_t dst = lds_swizzle(new_u, G) * (uint32_t)sizeof(V2);
+                        char* xb = reinterpret_cast<char*>(xbuf);
 #pragma unroll
-                    for (int v = 0; v < NV; v++) {
+                        for (int v = 0; v < NV; v++) {
 #pragma unroll
-                        for (int h = 0; h < 2; h++) {
-                            __syncthreads();
+                            for (int h = 0; h < 2; h++) {
+                                __syncthreads();
 #pragma unroll
-                            for (int q = 0; q < NH; q++) {
-                                const int r = h * NH + q;
-                                V2 x;
-                                x.x = vr[v][r];
-                                x.y = vi[v][r];
-                                xbuf[src ^ L->reg_lds[r]] = x;
-                            }
-                            __syncthreads();
+                                for (int q = 0; q < NH; q++) {
+                                    const int r = h * NH + q;
+                                    V2 x;
+                                    x.x = vr[v][r];
+                                    x.y = vi[v][r];
+                                    *reinterpret_cast<V2*>(xb + (src ^ L->reg_lds[r])) = x;
+                                }
+                                __syncthreads();
 #pragma unroll
-                            for (int q = 0; q < NH; q++) {
-                                const int r = h * NH + q;
-                                const V2 x = xbuf[dst ^ Lt->reg_lds[r]];
-                                vr[v][r] = x.x;
-                                vi[v][r] = x.y;
+                                for (int q = 0; q < NH; q++) {
+                                    const int r = h * NH + q;
+                                    const V2 x = *reinterpret_cast<const V2*>(xb + (dst ^ Lt->reg_lds[r]));
+                                    vr[v][r] = x.x;
+                                    vi[v][r] = x.y;
+                                }
                             }
                         }
+                        cur = j;
+                        L = Lt;
+                        thr_u = new_u;
+                        thr_goff = tg.gmap(thr_u);
                     }
-                    cur = j;
-                    L = Lt;
-                    thr_u = new_u;
-                    thr_goff = tg.gmap(thr_u);
-                }
-                const int act = fwd ? L->act_fwd : L->act_bwd;
-                mix_round<Real, R, NV>(vr, vi, act, op.flags, (Real)op.a, op.b, pend, gsum);
-            };
-            if constexpr (KC > 0) {
+                    const int act = fwd ? L->act_fwd : L->act_bwd;
+                    mix_round<Real, R, NV>(vr, vi, act, op.flags, (Real)op.a, op.b, pend, gsum);
+                };
+                if constexpr (KC > 0) {
 #pragma unroll
-                for (int step = 0; step < KC; step++) round(step);
-            } else {
-                for (int step = 0; step < K; step++) round(step);
-            }
-            if constexpr (NV == 2) {
-                if (op.flags & MIX_GBETA) wave_add<NS>(s_red, op.slot, gsum);
-            }
-        } else {  // OP_POINT
-            // Walk the registers in Gray-code order: consecutive registers differ in
-            // one bit k, so E changes by +-2 f[k] and the phase by exp(-+2i gamma f[k]).
-            double f[R];
-            const double e0 = thread_energy<R>(L, thr_u, s_g, s_ew, f);
-            const int fl = op.flags;
-            // E of register r = e0 + (Gray-walk sum of +-2 f[k]) + Q[r]
-            if (fl & (PT_REDUCE | PT_LAM_INIT | PT_GGAMMA)) {
-                double r_n = 0.0, r_e = 0.0, r_p = 0.0, r_g = 0.0;
-                double e_run = e0;
-#pragma unroll
-                for (int i = 0; i < NR; i++) {
-                    const int r = i ^ (i >> 1);
-                    if (i > 0) {
-                        const int k = __builtin_ctz(i);
-                        e_run += ((r >> k) & 1) ? 2.0 * f[k] : -2.0 * f[k];
-                    }
-                    const double e = e_run + L->Q[r];
-                    const double pr = (double)vr[0][r], pi = (double)vi[0][r];
-                    if (fl & PT_REDUCE) {
-                        const double p2 = pr * pr + pi * pi;
-                        r_n += p2;
-                        r_e += e * p2;
-                        if (fabs(e - a.emin) <= a.etol) r_p += p2;
-                    }
-                    if constexpr (NV == 2) {
-                        if (fl & PT_LAM_INIT) {
-                            vr[1][r] = (Real)(e * pr);
-                            vi[1][r] = (Real)(e * pi);
-                        }
-                        if (fl & PT_GGAMMA) {
-                            const Real q = vr[1][r] * vi[0][r] - vi[1][r] * vr[0][r];
-                            r_g += e * (double)q;
-                        }
-                    }
-                }
-                if (fl & PT_REDUCE) {
-                    const double s2 = pend[0] * pend[0];
-                    wave_add<NS>(s_red, op.slot, r_n * s2);
-                    wave_add<NS>(s_red, op.slot + 1, r_e * s2);
-                    wave_add<NS>(s_red, op.slot + 2, r_p * s2);
+                    for (int step = 0; step < KC; step++) round(step);
+                } else {
+                    for (int step = 0; step < K; step++) round(step);
                 }
                 if constexpr (NV == 2) {
-                    if (fl & PT_LAM_INIT) pend[1] = pend[0];
-                    if (fl & PT_GGAMMA) wave_add<NS>(s_red, op.slot2, r_g * pend[0] * pend[1]);
+                    if (op.flags & MIX_GBETA) wave_add<NS>(s_red, op.slot, gsum);
                 }
-            }
-            if (fl & (PT_PHASE_PSI | PT_PHASE_LAM)) {
-                const double gam = op.a;
-                const double2* __restrict__ qph = a.ptab + a.qph_off[op.qidx];
-                double2 gk[R];
-                double2 run;
-                if constexpr (INTE) {
-                    // integer energies: factors from the table exp(-i gamma m)
-                    const double2* __restrict__ lut = a.ptab + a.lut_off[op.qidx] + a.lut_half;
-                    const int Lh = a.lut_half;
+            } else {  // OP_POINT
+                // Walk the registers in Gray-code order: consecutive registers differ in
+                // one bit k, so E changes by +-2 f[k] and the phase by exp(-+2i gamma f[k]).
+                double f[R];
+                const double e0 = thread_energy<R, T - R>(L, geo, t, s_g, f);
+                const int fl = op.flags;
+                // E of register r = e0 + (Gray-walk sum of +-2 f[k]) + Q[r]
+                if (fl & (PT_REDUCE | PT_LAM_INIT | PT_GGAMMA)) {
+                    double r_n = 0.0, r_e = 0.0, r_p = 0.0, r_g = 0.0;
+                    double e_run = e0;
 #pragma unroll
-                    for (int k = 0; k < R; k++) {
-                        const int m = min(max((int)(2.0 * f[k]), -Lh), Lh);
-                        gk[k] = lut[m];
-                    }
-                    run = lut[min(max((int)e0, -Lh), Lh)];
-                } else {
-#pragma unroll
-                    for (int k = 0; k < R; k++) {
-                        double sn, cs;
-                        sincos(2.0 * gam * f[k], &sn, &cs);
-                        gk[k] = make_double2(cs, -sn);
-                    }
-                    double sn, cs;
-                    sincos(gam * e0, &sn, &cs);
-                    run = make_double2(cs, -sn);
-                }
-                double fac[NV];
-#pragma unroll
-                for (int v = 0; v < NV; v++) fac[v] = pend[v];
-#pragma unroll
-                for (int i = 0; i < NR; i++) {
-                    const int r = i ^ (i >> 1);
-                    if (i > 0) {
-                        const int k = __builtin_ctz(i);
-                        const double2 g = ((r >> k) & 1) ? gk[k] : make_double2(gk[k].x, -gk[k].y);
-                        run = cmul(run, g);
-                    }
-                    const double2 ph = cmul(run, qph[r]);
-#pragma unroll
-                    for (int v = 0; v < NV; v++) {
-                        const double pr = ph.x * fac[v], pim = ph.y * fac[v];
-                        if constexpr (sizeof(Real) == 8) {
-                            const double xr = vr[v][r], xi = vi[v][r];
-                            vr[v][r] = xr * pr - xi * pim;
-                            vi[v][r] = xr * pim + xi * pr;
-                        } else {
-                            const float cr = (float)pr, ci = (float)pim;
-                            const float xr = vr[v][r], xi = vi[v][r];
-                            vr[v][r] = xr * cr - xi * ci;
-                            vi[v][r] = xr * ci + xi * cr;
+                    for (int i = 0; i < NR; i++) {
+                        const int r = i ^ (i >> 1);
+                        if (i > 0) {
+                            const int k = __builtin_ctz(i);
+                            e_run += ((r >> k) & 1) ? 2.0 * f[k] : -2.0 * f[k];
+                        }
+                        const double e = e_run + L->Q[r];
+                        const double pr = (double)vr[0][r], pi = (double)vi[0][r];
+                        if (fl & PT_REDUCE) {
+                            const double p2 = pr * pr + pi * pi;
+                            r_n += p2;
+                            r_e += e * p2;
+                            if (fabs(e - a.emin) <= a.etol) r_p += p2;
+                        }
+                        if constexpr (NV == 2) {
+                            if (fl & PT_LAM_INIT) {
+                                vr[1][r] = (Real)(e * pr);
+                                vi[1][r] = (Real)(e * pi);
+                            }
+                            if (fl & PT_GGAMMA) {
+                                const Real q = vr[1][r] * vi[0][r] - vi[1][r] * vr[0][r];
+                                r_g += e * (double)q;
+                            }
                         }
                     }
+                    if (fl & PT_REDUCE) {
+                        const double s2 = pend[0] * pend[0];
+                        wave_add<NS>(s_red, op.slot, r_n * s2);
+                        wave_add<NS>(s_red, op.slot + 1, r_e * s2);
+                        wave_add<NS>(s_red, op.slot + 2, r_p * s2);
+                    }
+                    if constexpr (NV == 2) {
+                        if (fl & PT_LAM_INIT) pend[1] = pend[0];
+                        if (fl & PT_GGAMMA) wave_add<NS>(s_red, op.slot2, r_g * pend[0] * pend[1]);
+                    }
                 }
+                if (fl & (PT_PHASE_PSI | PT_PHASE_LAM)) {
+                    const double gam = op.a;
+                    const double2* __restrict__ qph = a.ptab + a.qph_off[op.qidx];
+                    double2 gk[R];
+                    double2 run;
+                    if constexpr (INTE) {
+                        // integer energies: factors from the table exp(-i gamma m)
+                        const double2* __restrict__ lut = a.ptab + a.lut_off[op.qidx] + a.lut_half;
+                        const int Lh = a.lut_half;
 #pragma unroll
-                for (int v = 0; v < NV; v++) pend[v] = 1.0;
+                        for (int k = 0; k < R; k++) {
+                            const int m = min(max((int)(2.0 * f[k]), -Lh), Lh);
+                            gk[k] = lut[m];
+                        }
+                        run = lut[min(max((int)e0, -Lh), Lh)];
+                    } else {
+                        // One sincos at a time: the fma(0, previous sine, x) link (exact
+                        // for finite values) keeps the scheduler from interleaving the
+                        // R + 1 evaluations, which would exhaust the register file.
+                        double link = 0.0;
+#pragma unroll
+                        for (int k = 0; k < R; k++) {
+                            double sn, cs;
+                            sincos(fma(0.0, link, 2.0 * gam * f[k]), &sn, &cs);
+                            gk[k] = make_double2(cs, -sn);
+                            link = sn;
+                        }
+                        double sn, cs;
+                        sincos(fma(0.0, link, gam * e0), &sn, &cs);
+                        run = make_double2(cs, -sn);
+                    }
+                    double fac[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; v++) fac[v] = pend[v];
+#pragma unroll
+                    for (int i = 0; i < NR; i++) {
+                        const int r = i ^ (i >> 1);
+                        if (i > 0) {
+                            const int k = __builtin_ctz(i);
+                            const double2 g = ((r >> k) & 1) ? gk[k] : make_double2(gk[k].x, -gk[k].y);
+                            run = cmul(run, g);
+                        }
+                        const double2 ph = cmul(run, qph[r]);
+#pragma unroll
+                        for (int v = 0; v < NV; v++) {
+                            const double pr = ph.x * fac[v], pim = ph.y * fac[v];
+                            if constexpr (sizeof(Real) == 8) {
+                                const double xr = vr[v][r], xi = vi[v][r];
+                                vr[v][r] = xr * pr - xi * pim;
+                                vi[v][r] = xr * pim + xi * pr;
+                            } else {
+                                const float cr = (float)pr, ci = (float)pim;
+                                const float xr = vr[v][r], xi = vi[v][r];
+                                vr[v][r] = xr * cr - xi * ci;
+                                vi[v][r] = xr * ci + xi * cr;
+                            }
+                        }
+                    }
+#pragma unroll
+                    for (int v = 0; v < NV; v++) pend[v] = 1.0;
+                }
             }
         }
-    }
 
-    // ---- store in the current layout (applying what is left of the pending scales)
+        // ---- store in the current layout (applying what is left of the pending scales)
 #pragma unroll
-    for (int v = 0; v < NV; v++) {
-        if (!(a.store & (1 << v))) continue;
-        V2* __restrict__ dst = (v == 0 ? psi : lam) + (base | thr_goff);
-        const Real sc = (Real)pend[v];
-        const bool unit = pend[v] == 1.0;
+        for (int v = 0; v < NV; v++) {
+            if (!(a.store & (1 << v))) continue;
+            V2* __restrict__ dst = (v == 0 ? psi : lam) + (base | thr_goff);
+            const Real sc = (Real)pend[v];
+            const bool unit = pend[v] == 1.0;
+            if (NTM & 2) {
 #pragma unroll
-        for (int r = 0; r < NR; r++) {
-            if constexpr (PH) {
-                if (((thr_u | L->reg_u[r]) & a.phantom) != 0u) continue;
+                for (int r = 0; r < NR; r++) {
+                    V2 x;
+                    x.x = unit ? vr[v][r] : vr[v][r] * sc;
+                    x.y = unit ? vi[v][r] : vi[v][r] * sc;
+                    st_nt(dst + L->reg_goff[r], x);
+                }
+            } else {
+#pragma unroll
+                for (int r = 0; r < NR; r++) {
+                    if constexpr (PH) {
+                        if (((thr_u | L->reg_u[r]) & a.phantom) != 0u) continue;
+                    }
+                    V2 x;
+                    x.x = unit ? vr[v][r] : vr[v][r] * sc;
+                    x.y = unit ? vi[v][r] : vi[v][r] * sc;
+                    dst[L->reg_goff[r]] = x;
+                }
             }
-            V2 x;
-            x.x = unit ? vr[v][r] : vr[v][r] * sc;
-            x.y = unit ? vi[v][r] : vi[v][r] * sc;
-            dst[L->reg_goff[r]] = x;
         }
-    }
 
-    // ---- per-tile partial sums, fixed order
-    if (a.nslots > 0) {
-        __syncthreads();
-        if ((int)t < a.nslots) {
-            double v = 0.0;
-            for (int ww = 0; ww < NW; ww++) v += s_red[ww][t];
-            a.partials[tile * (uint64_t)a.nslots + t] = v;
+        // ---- per-tile partial sums, fixed order
+        if (a.nslots > 0) {
+            __syncthreads();
+            if ((int)t < a.nslots) {
+                double v = 0.0;
+                for (int ww = 0; ww < NW; ww++) v += s_red[ww][t];
+                a.partials[tile * (uint64_t)a.nslots + t] = v;
+            }
         }
-    }
+        if constexpr (!PERSIST) break;
+        tile += gridDim.x;
+        if (tile < a.ntiles) __syncthreads();  // LDS reuse by the next tile
+    } while (tile < a.ntiles);
 }
 
 // Column sums of partials[nrows][nslots] in a fixed order: out[dst[s]] (+)= sum.
@@ -532,8 +614,7 @@ __global__ void __launch_bounds__(1 << (T - R)) k_ground(const GroundArgs a) {
     constexpr int NW = NT / 64;
     constexpr int RLO = (R + 1) / 2;
     constexpr int RHI = R - RLO;
-    __shared__ double s_g[kMaxT];
-    __shared__ double s_ew;
+    __shared__ double s_g[kTF];
     __shared__ double s_e[NW];
     __shared__ unsigned long long s_c[NW], s_a[NW];
 
@@ -542,14 +623,14 @@ __global__ void __launch_bounds__(1 << (T - R)) k_ground(const GroundArgs a) {
     const GeoBuf* __restrict__ geo = a.geo;
     const TileGeom tg{a.c, a.lo, a.g};
     const uint64_t base = tg.base(tile);
-    if (t < 64) tile_fields(a.is, geo, tg, base, T, s_g, &s_ew);
+    if (t < kTF) s_g[t] = a.tf[tile * kTF + t];
     __syncthreads();
 
     const GeoLayout* L = &geo->L[0];
-    const uint32_t thr_u = thread_index_bits(t, L);
+    const uint32_t thr_u = thread_index_bits<T - R>(t, L->tmask);
     const uint64_t thr_goff = tg.gmap(thr_u);
     double f[R];
-    const double e0 = thread_energy<R>(L, thr_u, s_g, s_ew, f);
+    const double e0 = thread_energy<R, T - R>(L, geo, t, s_g, f);
     double elo[1 << RLO], ehi[1 << RHI];
     elo[0] = e0;
 #pragma unroll
@@ -661,16 +742,39 @@ Shape shape_for(int dtype, int nv, bool grad) {
 // + 1 gradient slot, or 3 gradient slots).
 template <typename Real, int T, int R, int NV, int NS, int MINB>
 static int run_pass(const PassArgs& a, void* stream) {
-    const dim3 grid((unsigned)a.ntiles), block(1 << (T - R));
+    // persistent grids exist for the one-vector fast paths with >= 2 layouts
+    const bool pers = NV == 1 && a.grid > 0 && (uint64_t)a.grid < a.ntiles && a.nlayouts >= 2 && a.phantom == 0 &&
+                      (a.lut_half >= 0 || a.nphase == 0);
+    const unsigned nwg = pers ? (unsigned)a.grid : (unsigned)a.ntiles;
+    const dim3 grid(nwg), block(1 << (T - R));
     hipStream_t st = (hipStream_t)stream;
     const bool fast = a.phantom == 0 && (a.lut_half >= 0 || a.nphase == 0);
     if (fast) {
         // one or two layouts: straight-line walks; three or more: a loop keeps
         // the register pressure below the two-workgroups-per-CU limit
+        // (nontemporal variants for passes over long contiguous runs)
+        if constexpr (NV == 1) {
+            if (pers) {
+                if (a.nlayouts == 2)
+                    hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 2, 0, true>), grid, block, 0, st,
+                                       a);
+                else if (a.nt == 3)
+                    hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 0, 3, true>), grid, block, 0, st,
+                                       a);
+                else
+                    hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 0, 0, true>), grid, block, 0, st,
+                                       a);
+                return (int)hipGetLastError();
+            }
+        }
         if (a.nlayouts == 1)
             hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 1>), grid, block, 0, st, a);
+        else if (a.nlayouts == 2 && a.nt == 3)
+            hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 2, 3>), grid, block, 0, st, a);
         else if (a.nlayouts == 2)
             hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 2>), grid, block, 0, st, a);
+        else if (a.nt == 3)
+            hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 0, 3>), grid, block, 0, st, a);
         else
             hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 0>), grid, block, 0, st, a);
     } else if (a.lut_half >= 0) {
@@ -713,6 +817,13 @@ int launch_reduce_slots(const double* partials, uint64_t nrows, int nslots, cons
     for (int s = 0; s < kMaxSlots; s++) d.d[s] = s < nslots ? dst[s] : 0;
     hipLaunchKernelGGL(k_reduce_slots, dim3(nslots), dim3(256), 0, (hipStream_t)stream, partials, nrows, nslots,
                        d, accumulate, out);
+    return (int)hipGetLastError();
+}
+
+int launch_tile_fields(const TfArgs& a, void* stream) {
+    const uint64_t blocks = (a.ntiles + 3) / 4;
+    const unsigned grid = (unsigned)(blocks < 65536 ? blocks : 65536);
+    hipLaunchKernelGGL(k_tile_fields, dim3(grid), dim3(256), 0, (hipStream_t)stream, a);
     return (int)hipGetLastError();
 }
 

@@ -269,6 +269,28 @@ def test_grad_from_forward_state(sv, orc, dtype):
     assert np.max(np.abs(db - rb)) <= GRAD_TOL[dtype] * scale
 
 
+@pytest.mark.parametrize("first", ["c128", "c64"])
+def test_one_instance_both_dtypes(sv, orc, first):
+    """Regression: tile tables cached per instance must not be shared between
+    amplitude types (complex128 forward passes and complex64 adjoint passes use
+    the same tile shape but different LDS swizzles and byte strides)."""
+    n, p = 16, 2
+    inst = instance_for(n, "int", 150)
+    H = sv.Ising.from_instance(inst)
+    g, b = I.linear_ramp_params(p)
+    f, rg, rb = orc.grad_tangent(inst, g, b)
+    scale = max(np.max(np.abs(np.concatenate([rg, rb]))), orc.coeff_scale(inst))
+    ref = orc.qaoa_state(inst, g, b)
+    for dtype in ([first, "c64" if first == "c128" else "c128"] * 2):
+        psi = sv.State(n, dtype)
+        sv.qaoa_forward(psi, H, g, b)
+        assert np.max(np.abs(psi.to_numpy() - ref)) <= AMP_TOL[dtype]
+        lam = sv.State(n, dtype)
+        e, dg, db = sv.grad(psi, lam, H, g, b)
+        assert np.max(np.abs(dg - rg)) <= GRAD_TOL[dtype] * scale
+        assert np.max(np.abs(db - rb)) <= GRAD_TOL[dtype] * scale
+
+
 def test_grad_errors(sv):
     H = sv.Ising.from_instance(instance_for(10, "int", 1))
     a = sv.State(10, "c128")
