@@ -3,8 +3,10 @@
 Workload (the one the headline metric is quoted on): p = 4 QAOA layers at
 n = 32 qubits, complex128 amplitudes (64 GiB state), on a random Ising instance
 G(32, 64) with integer J in [-2, 2] and h in {-1, 0, 1} (seeded), followed by
-<H_C> and the ground-state probability.  One step = sv_qaoa_forward(p = 4) +
-sv_expect.  value = amplitude updates per second = p * 2^n * (n + 1) / t_step
+<H_C> and the ground-state probability.  One step = one energy evaluation of
+the QAOA objective, sv_qaoa_energy(p = 4): the forward circuit with the
+observables fused into its last pass (the final state is stored).
+value = amplitude updates per second = p * 2^n * (n + 1) / t_step
 (n butterflies and one phase per amplitude per layer).
 
 Also reported (outside the timed steps): roofline of the dominant kernel
@@ -82,8 +84,7 @@ def main():
     stream = torch.cuda.current_stream()
 
     def step():
-        sv.qaoa_forward(s, H, gam, bet)
-        return sv.expect(s, H)
+        return sv.qaoa_energy(s, H, gam, bet)
 
     for i in range(args.warmup):
         step()
@@ -133,13 +134,11 @@ def main():
         del lam
         # complex64 storage, same instance
         s64 = sv.State(n, "c64")
-        sv.qaoa_forward(s64, H, gam, bet)
-        sv.expect(s64, H)
+        sv.qaoa_energy(s64, H, gam, bet)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(args.steps):
-            sv.qaoa_forward(s64, H, gam, bet)
-            o64 = sv.expect(s64, H)
+            o64 = sv.qaoa_energy(s64, H, gam, bet)
         torch.cuda.synchronize()
         ms64 = (time.perf_counter() - t0) * 1e3 / args.steps
         extras["c64"] = {"ms_per_step": round(ms64, 3), "amp_updates_per_s": updates / (ms64 * 1e-3),
@@ -164,7 +163,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.dtype == "c128" else "f32",
         "data": "synthetic",
-        "config": {"workload": f"QAOA p={p} forward + <H_C>/P_gs, n={n} {args.dtype}, random Ising G(n,2n) "
+        "config": {"workload": f"QAOA p={p} energy evaluation (forward + fused <H_C>/P_gs), n={n} {args.dtype}, random Ising G(n,2n) "
                                f"J in [-2,2], h in {{-1,0,1}}", "n": n, "p": p, "amp_dtype": args.dtype},
         "roofline": roof,
         "cpu_baseline": cpu,

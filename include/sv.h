@@ -130,6 +130,15 @@ int sv_mixer(sv_state s, double beta);
 int sv_qaoa_forward(sv_state s, sv_ising H, int p, const double* gamma, const double* beta,
                     int from_plus);
 
+/* One energy evaluation of the QAOA objective (Sec. III.B.1: each optimiser
+ * call returns <H_C> of the p-layer state): sv_qaoa_forward followed by the
+ * observables of sv_expect, with the reductions fused into the circuit's
+ * last tile pass instead of a separate read of the state.  The final state
+ * is stored as by sv_qaoa_forward.  Any output pointer may be NULL.
+ * Synchronises the stream.  Errors as sv_qaoa_forward. */
+int sv_qaoa_energy(sv_state s, sv_ising H, int p, const double* gamma, const double* beta, int from_plus,
+                   double* energy, double* p_gs, double* norm);
+
 /* Approximate quantum annealing (Sec. III.B.2): the same circuit, from |+>^n,
  * with `steps` (gamma_k, beta_k) pairs built by one of the schedule helpers
  * below.  If pgs_per_step / energy_per_step are non-NULL they receive, after

@@ -53,6 +53,7 @@ std::map<std::string, int> g_knobs = {
     {"ntmin", 6},     // passes whose contiguous runs hold >= 2^ntmin amplitudes stream with nontemporal hints
     {"persist", 0},   // tile passes: workgroups per CU of a persistent grid (0: one workgroup per tile)
     {"stagger", 0},   // persistent grids: start delay of the second half (units of 64*127 clocks)
+    {"snake", 1},     // 1: the contiguous tile group takes a middle slot of the layer's group order
 };
 int knob(const char* k) {
     std::lock_guard<std::mutex> g(g_knob_mu);
@@ -119,6 +120,7 @@ extern "C" int sv_tune_set(const char* name, int value) {
         return fail(SV_ERR_ARG, "%s must be in [0, 8]", name);
     if (std::string(name) == "ntmin" && (value < 0 || value > 64)) return fail(SV_ERR_ARG, "ntmin must be in [0, 64]");
     if (std::string(name) == "persist" && (value < 0 || value > 8)) return fail(SV_ERR_ARG, "persist must be in [0, 8]");
+    if (std::string(name) == "snake" && (value < 0 || value > 1)) return fail(SV_ERR_ARG, "snake must be 0 or 1");
     if (std::string(name) == "stagger" && (value < 0 || value > 64)) return fail(SV_ERR_ARG, "stagger must be in [0, 64]");
     it->second = value;
     return SV_OK;
@@ -1289,10 +1291,28 @@ extern "C" int sv_cost_phase(sv_state s, sv_ising H, double gamma) {
     return run_program(s, nullptr, H, prog, plan, false);
 }
 
-static void push_mixer(std::vector<Event>& ev, int ngroups, double beta, bool reversed, int vec, int res) {
-    for (int i = 0; i < ngroups; i++) {
+// Order in which a layer visits the tile groups.  Odd layers walk it forward
+// and even layers backward (snake), so the end groups of consecutive layers
+// share a pass while every middle group costs one pass per layer.  The
+// contiguous group A streams fastest, so it takes a middle position.
+static std::vector<int> group_order(int ngroups, int dt, int n) {
+    std::vector<int> o;
+    if (ngroups <= 2 || knob_for("snake", dt, n) == 0) {
+        for (int i = 0; i < ngroups; i++) o.push_back(i);
+        return o;
+    }
+    o.push_back(1);
+    o.push_back(0);
+    for (int i = 2; i < ngroups; i++) o.push_back(i);
+    return o;
+}
+
+static void push_mixer(std::vector<Event>& ev, const std::vector<int>& order, double beta, bool reversed, int vec,
+                       int res) {
+    const int ng = (int)order.size();
+    for (int i = 0; i < ng; i++) {
         Event e{EV_MIX};
-        e.group = reversed ? ngroups - 1 - i : i;
+        e.group = order[reversed ? ng - 1 - i : i];
         e.angle = beta;
         e.vec = vec;
         e.res = res;
@@ -1305,7 +1325,7 @@ extern "C" int sv_mixer(sv_state s, double beta) {
     if (!std::isfinite(beta)) return fail(SV_ERR_NUMERIC, "sv_mixer: beta is not finite");
     Plan plan = make_plan(s->n, s->dt);
     std::vector<Event> ev;
-    push_mixer(ev, (int)plan.by_nv[1].size(), beta, false, 1, -1);
+    push_mixer(ev, group_order((int)plan.by_nv[1].size(), 0, s->n), beta, false, 1, -1);
     Program prog = build_program(ev, 0, true);
     return run_program(s, nullptr, nullptr, prog, plan, false);
 }
@@ -1313,14 +1333,14 @@ extern "C" int sv_mixer(sv_state s, double beta) {
 // Forward circuit events: layer k applies the phase then the mixer groups in
 // snake order (odd layers ascending, even layers descending), so consecutive
 // layers meet on the same tile group and share a pass.
-static void forward_events(std::vector<Event>& ev, int ngroups, int p, const double* gamma, const double* beta,
-                           bool from_plus, int reduce_every_step_base) {
+static void forward_events(std::vector<Event>& ev, const std::vector<int>& order, int p, const double* gamma,
+                           const double* beta, bool from_plus, int reduce_every_step_base) {
     if (from_plus) ev.push_back(Event{EV_INIT});
     for (int k = 0; k < p; k++) {
         Event ph{EV_PHASE};
         ph.angle = gamma[k];
         ev.push_back(ph);
-        push_mixer(ev, ngroups, beta[k], (k % 2) == 1, 1, -1);
+        push_mixer(ev, order, beta[k], (k % 2) == 1, 1, -1);
         if (reduce_every_step_base >= 0) {
             Event r{EV_REDUCE};
             r.res = reduce_every_step_base + 3 * k;
@@ -1337,9 +1357,32 @@ extern "C" int sv_qaoa_forward(sv_state s, sv_ising H, int p, const double* gamm
     if (rc) return rc;
     Plan plan = make_plan(s->n, s->dt);
     std::vector<Event> ev;
-    forward_events(ev, (int)plan.by_nv[1].size(), p, gamma, beta, from_plus != 0, -1);
+    forward_events(ev, group_order((int)plan.by_nv[1].size(), (int)s->dt, s->n), p, gamma, beta, from_plus != 0, -1);
     Program prog = build_program(ev, 0, knob_for("fuse", (int)s->dt, s->n) != 0);
     return run_program(s, nullptr, H, prog, plan, false);
+}
+
+extern "C" int sv_qaoa_energy(sv_state s, sv_ising H, int p, const double* gamma, const double* beta,
+                              int from_plus, double* energy, double* p_gs, double* norm) {
+    int rc = check_pair(s, H, "sv_qaoa_energy");
+    if (rc) return rc;
+    rc = check_angles(p, gamma, beta, "sv_qaoa_energy");
+    if (rc) return rc;
+    Plan plan = make_plan(s->n, s->dt);
+    std::vector<Event> ev;
+    forward_events(ev, group_order((int)plan.by_nv[1].size(), (int)s->dt, s->n), p, gamma, beta, from_plus != 0, -1);
+    Event r{EV_REDUCE};
+    r.res = 0;
+    ev.push_back(r);  // merges into the last mixer pass as its point op
+    Program prog = build_program(ev, 3, knob_for("fuse", (int)s->dt, s->n) != 0);
+    rc = run_program(s, nullptr, H, prog, plan, true);
+    if (rc) return rc;
+    rc = fetch_results(s, 3);
+    if (rc) return rc;
+    if (norm) *norm = s->w.h_res[0];
+    if (energy) *energy = s->w.h_res[1];
+    if (p_gs) *p_gs = s->w.h_res[2];
+    return SV_OK;
 }
 
 extern "C" int sv_aqa_run(sv_state s, sv_ising H, int steps, const double* gamma, const double* beta,
@@ -1351,7 +1394,8 @@ extern "C" int sv_aqa_run(sv_state s, sv_ising H, int steps, const double* gamma
     const bool want = pgs_per_step || energy_per_step;
     Plan plan = make_plan(s->n, s->dt);
     std::vector<Event> ev;
-    forward_events(ev, (int)plan.by_nv[1].size(), steps, gamma, beta, true, want ? 0 : -1);
+    forward_events(ev, group_order((int)plan.by_nv[1].size(), (int)s->dt, s->n), steps, gamma, beta, true,
+                   want ? 0 : -1);
     Program prog = build_program(ev, want ? 3 * steps : 0, knob_for("fuse", (int)s->dt, s->n) != 0);
     rc = run_program(s, nullptr, H, prog, plan, want);
     if (rc || !want) return rc;
@@ -1400,16 +1444,16 @@ extern "C" int sv_grad(sv_state psi, sv_state lam, sv_ising H, int p, const doub
     if (lam->failed) return fail(SV_ERR_HIP, "lam state is in a failed state");
     // both vectors share one tile geometry: plan with the two-vector shape
     Plan plan = make_plan(psi->n, psi->dt, true);
-    const int G = (int)plan.by_nv[1].size();
+    const std::vector<int> order = group_order((int)plan.by_nv[1].size(), (int)psi->dt, psi->n);
     std::vector<Event> ev;
-    if (!psi_is_forward) forward_events(ev, G, p, gamma, beta, true, -1);
+    if (!psi_is_forward) forward_events(ev, order, p, gamma, beta, true, -1);
     Event r{EV_REDUCE};
     r.res = 0;
     ev.push_back(r);
     ev.push_back(Event{EV_LAMINIT});
     for (int k = p - 1; k >= 0; k--) {
         // undo the mixer of layer k (groups in the reverse of their forward order)
-        push_mixer(ev, G, -beta[k], (k % 2) == 0, 3, 3 + p + k);
+        push_mixer(ev, order, -beta[k], (k % 2) == 0, 3, 3 + p + k);
         Event gg{EV_GGAMMA};
         gg.res = 3 + k;
         ev.push_back(gg);

@@ -50,6 +50,7 @@ def _load():
         "sv_cost_phase": (ip, [vp, vp, ctypes.c_double]),
         "sv_mixer": (ip, [vp, ctypes.c_double]),
         "sv_qaoa_forward": (ip, [vp, vp, ip, dp, dp, ip]),
+        "sv_qaoa_energy": (ip, [vp, vp, ip, dp, dp, ip, dp, dp, dp]),
         "sv_aqa_run": (ip, [vp, vp, ip, dp, dp, dp, dp]),
         "sv_expect": (ip, [vp, vp, dp, dp, dp]),
         "sv_grad": (ip, [vp, vp, vp, ip, dp, dp, ip, dp, dp, dp]),
@@ -230,6 +231,17 @@ def qaoa_forward(s: State, H: Ising, gamma, beta, from_plus: bool = True) -> Non
     if len(g) != len(b):
         raise ValueError("gamma and beta must have equal length")
     _check(lib.sv_qaoa_forward(s.handle, H.handle, len(g), _dp(g), _dp(b), int(bool(from_plus))))
+
+
+def qaoa_energy(s: State, H: Ising, gamma, beta, from_plus: bool = True):
+    """QAOA forward with the observables fused into its last pass: (energy, p_gs, norm)."""
+    g, b = _f64(gamma), _f64(beta)
+    if len(g) != len(b):
+        raise ValueError("gamma and beta must have equal length")
+    e, p, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    _check(lib.sv_qaoa_energy(s.handle, H.handle, len(g), _dp(g), _dp(b), int(bool(from_plus)), ctypes.byref(e),
+                              ctypes.byref(p), ctypes.byref(n)))
+    return e.value, p.value, n.value
 
 
 def aqa_run(s: State, H: Ising, gamma, beta, per_step: bool = False):

@@ -146,6 +146,28 @@ def test_qaoa_forward_and_expect(sv, orc, dtype, n, p):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [3, 13, 16, 21])
+def test_qaoa_energy_fused(sv, orc, dtype, n):
+    """Forward with the observables fused into the last pass equals forward,
+    then expect, and the oracle; the stored state is the forward state."""
+    p = 3
+    inst = instance_for(n, "int" if n % 2 else "real", 160 + n)
+    H = sv.Ising.from_instance(inst)
+    g, b = I.uniform_params(p, 170 + n, -1.0, 1.0)
+    E = orc.energies(inst)
+    ref = orc.qaoa_state(inst, g, b, E=E)
+    ro = orc.observables(inst, ref, E=E)
+    s = sv.State(n, dtype)
+    e, pg, nrm = sv.qaoa_energy(s, H, g, b)
+    assert np.max(np.abs(s.to_numpy() - ref)) <= AMP_TOL[dtype]
+    assert abs(e - ro[1]) <= energy_tol(orc, inst, ro[1])
+    assert abs(pg - ro[2]) <= PROB_TOL[dtype]
+    assert abs(nrm - 1.0) <= (1e-12 if dtype == "c128" else 1e-5)
+    e2, pg2, nrm2 = sv.expect(s, H)
+    assert abs(e - e2) <= energy_tol(orc, inst, ro[1]) and abs(pg - pg2) <= PROB_TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("n", [6, 14, 18])
 def test_qaoa_from_given_state(sv, orc, dtype, n):
     inst = instance_for(n, "int", 70 + n)
@@ -190,6 +212,35 @@ def test_fusion_plans_agree(sv, orc, dtype):
     finally:
         sv.tune_set("fuse", 1)
     assert np.max(np.abs(a.to_numpy() - c.to_numpy())) <= AMP_TOL[dtype] / 10
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_group_orders_agree(sv, orc, dtype):
+    """Three tile groups: index-order and middle-A snake schedules give the same
+    state, energy and gradient (the mixer factors of one layer commute)."""
+    n = 24 if dtype == "c128" else 26
+    assert len(sv.describe(n, dtype)["plans"]["nv1"]) == 3
+    inst = instance_for(n, "int", 82)
+    H = sv.Ising.from_instance(inst)
+    g, b = I.uniform_params(3, 83)
+    out = {}
+    for snake in (1, 0):
+        sv.tune_set("snake", snake)
+        try:
+            a = sv.State(n, dtype)
+            e = sv.qaoa_energy(a, H, g, b)
+            lam = sv.State(n, dtype)
+            psi = sv.State(n, dtype)
+            gr = sv.grad(psi, lam, H, g, b)
+            out[snake] = (a.to_numpy(), e, gr)
+        finally:
+            sv.tune_set("snake", 1)
+    (a1, e1, g1), (a0, e0, g0) = out[1], out[0]
+    assert np.max(np.abs(a1 - a0)) <= AMP_TOL[dtype] / 10
+    assert abs(e1[0] - e0[0]) <= energy_tol(orc, inst, e0[0])
+    scale = orc.coeff_scale(inst)
+    assert np.max(np.abs(g1[1] - g0[1])) <= GRAD_TOL[dtype] * scale
+    assert np.max(np.abs(g1[2] - g0[2])) <= GRAD_TOL[dtype] * scale
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
