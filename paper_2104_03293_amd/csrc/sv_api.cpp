@@ -54,6 +54,7 @@ std::map<std::string, int> g_knobs = {
     {"persist", 0},   // tile passes: workgroups per CU of a persistent grid (0: one workgroup per tile)
     {"stagger", 0},   // persistent grids: start delay of the second half (units of 64*127 clocks)
     {"snake", 1},     // 1: the contiguous tile group takes a middle slot of the layer's group order
+    {"dpp", 1},       // 1: one active bit may be butterflied across lanes to save a layout
 };
 int knob(const char* k) {
     std::lock_guard<std::mutex> g(g_knob_mu);
@@ -120,7 +121,8 @@ extern "C" int sv_tune_set(const char* name, int value) {
         return fail(SV_ERR_ARG, "%s must be in [0, 8]", name);
     if (std::string(name) == "ntmin" && (value < 0 || value > 64)) return fail(SV_ERR_ARG, "ntmin must be in [0, 64]");
     if (std::string(name) == "persist" && (value < 0 || value > 8)) return fail(SV_ERR_ARG, "persist must be in [0, 8]");
-    if (std::string(name) == "snake" && (value < 0 || value > 1)) return fail(SV_ERR_ARG, "snake must be 0 or 1");
+    if ((std::string(name) == "snake" || std::string(name) == "dpp") && (value < 0 || value > 1))
+        return fail(SV_ERR_ARG, "%s must be 0 or 1", name);
     if (std::string(name) == "stagger" && (value < 0 || value > 64)) return fail(SV_ERR_ARG, "stagger must be in [0, 64]");
     it->second = value;
     return SV_OK;
@@ -242,8 +244,9 @@ struct sv_state_s {
 // the byte strides stored in the table.
 struct GeoKey {
     int T, R, c, lo, g, n, dt;
+    uint64_t layouts;  // signature of the register blocks and lane butterflies (plan knobs change them)
     bool operator<(const GeoKey& o) const {
-        return std::tie(T, R, c, lo, g, n, dt) < std::tie(o.T, o.R, o.c, o.lo, o.g, o.n, o.dt);
+        return std::tie(T, R, c, lo, g, n, dt, layouts) < std::tie(o.T, o.R, o.c, o.lo, o.g, o.n, o.dt, o.layouts);
     }
 };
 
@@ -296,6 +299,7 @@ struct Geometry {
     uint64_t ntiles;
     std::vector<std::vector<int>> blocks;  // register bit blocks per layout
     std::vector<uint32_t> act_fwd, act_bwd;
+    std::vector<uint32_t> dpp;  // per layout: lane positions butterflied across lanes (bit 3 or 4)
 };
 
 static uint32_t swizzle(uint32_t u, int G) {
@@ -316,7 +320,7 @@ static int swz_bits(sv_dtype d) { return d == SV_C128 ? 3 : 4; }
 // remaining active bits are covered from the top with blocks that start at or
 // above the swizzle width G, so the last layout again has the carriers as its
 // lowest lane bits (coalesced stores).
-static Geometry make_geometry(int n, int T, int R, int c, int lo, int g, int G) {
+static Geometry make_geometry(int n, int T, int R, int c, int lo, int g, int G, uint32_t lane_pos_mask) {
     Geometry geo{};
     geo.T = T;
     geo.R = R;
@@ -374,8 +378,78 @@ static Geometry make_geometry(int n, int T, int R, int c, int lo, int g, int G) 
         if (m & active) keep.push_back(b);
     }
     if (keep.empty()) keep.push_back(blk[0]);
+    // One layout fewer: if every active bit but one (x) fits in K - 1 register
+    // blocks and x then sits at an allowed lane position of the last layout
+    // (lane_pos_mask: 3 = DPP row_ror:8, 4 = ds_swizzle xor 16), x is
+    // butterflied across lanes there instead of through another LDS exchange.
+    // The last layout keeps the lowest tile bits as its lowest lanes
+    // (coalesced stores).
+    std::vector<uint32_t> dpp(keep.size(), 0u);
+    if (lane_pos_mask != 0 && (keep.size() >= 3 || (keep.size() == 2 && !groupA))) {
+        const int K0 = (int)keep.size();
+        uint32_t b0 = 0;
+        for (int l : keep[0]) b0 |= 1u << l;
+        std::vector<int> U;
+        for (int l = 0; l < T; l++)
+            if ((active >> l & 1u) && !(b0 >> l & 1u)) U.push_back(l);
+        const int nlow = groupA ? std::min(G, F) : c;  // tile bits that stay the lowest lanes at the end
+        auto in = [](const std::vector<int>& v, int l) { return std::find(v.begin(), v.end(), l) != v.end(); };
+        // pad a block to F free bits with bits that need no butterfly here
+        auto pad = [&](std::vector<int>& b, int x, bool last) {
+            for (int l = T - 2; l >= 0 && (int)b.size() < F; l--) {
+                if (in(b, l) || l == x || (last && l < nlow)) continue;
+                if ((active >> l & 1u) && !(b0 >> l & 1u)) continue;  // only inactive or first-layout bits
+                b.push_back(l);
+            }
+            return (int)b.size() == F;
+        };
+        bool found = false;
+        for (size_t xi = 0; xi < U.size() && !found; xi++) {
+            const int x = U[xi];
+            std::vector<int> V;
+            for (int l : U)
+                if (l != x) V.push_back(l);
+            const int nv = (int)V.size();
+            const int m = (nv + F - 1) / F;  // register blocks after the first
+            if (m + 1 >= K0 || nv > 20) continue;
+            for (uint32_t sub = 0; sub < (1u << nv) && !found; sub++) {
+                if (__builtin_popcount(sub) != std::min(F, nv)) continue;
+                std::vector<int> last, mid;
+                for (int q = 0; q < nv; q++) (sub >> q & 1u ? last : mid).push_back(V[q]);
+                if ((int)mid.size() > (m - 1) * F) continue;
+                if (!pad(last, x, true)) continue;
+                uint32_t lm = 1u << (T - 1);
+                for (int l : last) lm |= 1u << l;
+                std::vector<int> tbits;
+                for (int l = 0; l < T; l++)
+                    if (!(lm >> l & 1u)) tbits.push_back(l);
+                bool ok = (int)tbits.size() >= 6;
+                for (int q = 0; q < nlow && ok; q++) ok = tbits[q] == q;
+                int pos = -1;
+                for (int q = 0; q < 6 && ok; q++)
+                    if (tbits[q] == x) pos = q;
+                if (!ok || pos < 0 || !(lane_pos_mask >> pos & 1u)) continue;
+                std::vector<std::vector<int>> nb{keep[0]};
+                bool good = true;
+                for (size_t q = 0; q < mid.size() && good; q += F) {
+                    std::vector<int> b(mid.begin() + q, mid.begin() + std::min(mid.size(), q + F));
+                    good = pad(b, x, false);
+                    b.push_back(T - 1);
+                    nb.push_back(b);
+                }
+                if (!good) continue;
+                last.push_back(T - 1);
+                nb.push_back(last);
+                keep = nb;
+                dpp.assign(keep.size(), 0u);
+                dpp.back() = 1u << pos;
+                found = true;
+            }
+        }
+    }
     const int K = (int)keep.size();
     geo.blocks = keep;
+    geo.dpp = dpp;
     geo.act_fwd.assign(K, 0);
     geo.act_bwd.assign(K, 0);
     uint32_t done = 0;
@@ -403,19 +477,21 @@ static Geometry make_geometry(int n, int T, int R, int c, int lo, int g, int G) 
 static std::vector<Geometry> plan_groups(int n, sv_dtype dt, int nv, bool grad = false) {
     const Shape sh = shape_for((int)dt, nv, grad);
     const int T = sh.T, R = sh.R, G = swz_bits(dt);
+    // lane positions the kernels butterfly across lanes: 3 (all tiles), 4 (14-bit complex64 tiles)
+    const uint32_t dpp = knob_for("dpp", (int)dt, n) == 0 ? 0u : (dt == SV_C64 && T == 14 ? 0x18u : 0x8u);
     std::vector<Geometry> out;
     if (n <= T) {
-        out.push_back(make_geometry(n, T, R, n, n, 0, G));
+        out.push_back(make_geometry(n, T, R, n, n, 0, G, dpp));
         return out;
     }
-    out.push_back(make_geometry(n, T, R, T, T, 0, G));
+    out.push_back(make_geometry(n, T, R, T, T, 0, G, dpp));
     const int cmin = std::max(G, knob_for(dt == SV_C128 ? "cmin128" : "cmin64", (int)dt, n));
     const int rest = n - T, gmax = T - cmin;
     const int ng = (rest + gmax - 1) / gmax;
     int lo = T;
     for (int i = 0; i < ng; i++) {
         int g = rest / ng + (i < rest % ng ? 1 : 0);
-        out.push_back(make_geometry(n, T, R, T - g, lo, g, G));
+        out.push_back(make_geometry(n, T, R, T - g, lo, g, G, dpp));
         lo += g;
     }
     return out;
@@ -463,6 +539,7 @@ static int build_geobuf(const Geometry& geo, const sv_ising_s* H, sv_dtype dt, G
             if (L.tmask >> l & 1u) tb.push_back(l);
         L.act_fwd = (int32_t)geo.act_fwd[j];
         L.act_bwd = (int32_t)geo.act_bwd[j];
+        L.dpp = (int32_t)geo.dpp[j];
         for (int r = 0; r < (1 << R); r++) {
             uint32_t u = 0;
             for (int k = 0; k < R; k++)
@@ -521,7 +598,13 @@ static std::mutex g_geo_mu;
 static std::map<GeoKey, GeoBuf*> g_plain_geos;  // instance-free tables (mixer-only passes)
 
 static int get_geobuf(const Geometry& geo, sv_ising_s* H, sv_dtype dt, GeoBuf** out) {
-    GeoKey key{geo.T, geo.R, geo.c, geo.lo, geo.g, geo.n, (int)dt};
+    uint64_t sig = 1469598103934665603ull;  // FNV-1a over the layout description
+    auto mix = [&](uint64_t v) { sig = (sig ^ v) * 1099511628211ull; };
+    for (size_t j = 0; j < geo.blocks.size(); j++) {
+        for (int l : geo.blocks[j]) mix((uint64_t)l);
+        mix(1000u + geo.dpp[j]);
+    }
+    GeoKey key{geo.T, geo.R, geo.c, geo.lo, geo.g, geo.n, (int)dt, sig};
     if (H) {
         std::lock_guard<std::mutex> g(H->mu);
         auto it = H->geos.find(key);
@@ -1564,7 +1647,8 @@ extern "C" int sv_tune_describe(int n, sv_dtype dtype, char* buf, size_t len) {
                 js += (j ? "," : "") + std::string("{\"bits\":[");
                 for (size_t k = 0; k < g.blocks[j].size(); k++)
                     js += (k ? "," : "") + std::to_string(g.blocks[j][k]);
-                js += "],\"fwd\":" + std::to_string(g.act_fwd[j]) + ",\"bwd\":" + std::to_string(g.act_bwd[j]) + "}";
+                js += "],\"fwd\":" + std::to_string(g.act_fwd[j]) + ",\"bwd\":" + std::to_string(g.act_bwd[j]) +
+                      ",\"dpp\":" + std::to_string(g.dpp[j]) + "}";
             }
             js += "]}";
         }

@@ -73,7 +73,7 @@ struct GeoLayout {
     uint32_t thr_off;       // per-thread coupling table: offset in doubles from the GeoBuf start (0: none)
     int32_t act_fwd;        // register slots butterflied when entering forward
     int32_t act_bwd;        // ... when walking the layouts backwards
-    int32_t pad;
+    int32_t dpp;            // lane positions (bits 0, 1, 3 of the lane id) butterflied across lanes here
     double Q[64];           // sum of couplings among register bits, per register r
 };
 

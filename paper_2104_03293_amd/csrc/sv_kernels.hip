@@ -189,6 +189,62 @@ __device__ __forceinline__ void butterfly(Real& ar, Real& ai, Real& br, Real& bi
     bi = nbi;
 }
 
+// Value of the lane whose id differs in one bit, per 32-bit word: lane bit 3
+// by a DPP row_ror:8 move (within a 16-lane row), lane bit 4 by a ds_swizzle
+// in bit mode (and 0x1f, xor 0x10 within 32 lanes; no LDS storage).
+constexpr int kLaneX8 = 0x128;
+constexpr int kLaneX16 = 0x10000 | (0x10 << 10) | 0x1f;
+template <int CTRL>
+__device__ __forceinline__ int lane_xor_word(int w) {
+    if constexpr (CTRL & 0x10000)
+        return __builtin_amdgcn_ds_swizzle(w, CTRL & 0xffff);
+    else
+        return __builtin_amdgcn_update_dpp(0, w, CTRL, 0xF, 0xF, true);
+}
+template <int CTRL>
+__device__ __forceinline__ float lane_xor(float x) {
+    return __int_as_float(lane_xor_word<CTRL>(__float_as_int(x)));
+}
+template <int CTRL>
+__device__ __forceinline__ double lane_xor(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = lane_xor_word<CTRL>((int)(b & 0xffffffffll));
+    const int hi = lane_xor_word<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Butterfly of one qubit held by a lane bit: both lanes of a pair apply
+// x <- x - i t x_partner (the same form for the upper and the lower member).
+// With gradient accumulation each lane adds Im(conj(lam_self) psi_partner), so
+// that the pair sum of the register form is split over the two lanes.
+template <int CTRL, typename Real, int R, int NV>
+__device__ __forceinline__ void lane_round(Real (&vr)[NV][1 << R], Real (&vi)[NV][1 << R], int flags, Real t,
+                                           double cosb, double (&pend)[NV], double& gsum) {
+    constexpr int NR = 1 << R;
+    if constexpr (NV == 2) {
+        if (flags & MIX_GBETA) {
+            double gb = 0.0;
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                const Real pr = lane_xor<CTRL>(vr[0][r]), pi = lane_xor<CTRL>(vi[0][r]);
+                gb += (double)(vr[1][r] * pi - vi[1][r] * pr);
+            }
+            gsum += gb * pend[0] * pend[1];
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; v++) {
+        if (!(flags & (1 << v))) continue;
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            const Real pr = lane_xor<CTRL>(vr[v][r]), pi = lane_xor<CTRL>(vi[v][r]);
+            vr[v][r] = fma(t, pi, vr[v][r]);
+            vi[v][r] = fma(-t, pr, vi[v][r]);
+        }
+        pend[v] *= cosb;
+    }
+}
+
 // Butterflies of every active register slot of the current layout; each slot
 // multiplies the pending scale of the touched vectors by cos(beta).  With
 // gradient accumulation the pair terms Im(conj(lam_a) psi_b) + Im(conj(lam_b) psi_a)
@@ -416,6 +472,21 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                     }
                     const int act = fwd ? L->act_fwd : L->act_bwd;
                     mix_round<Real, R, NV>(vr, vi, act, op.flags, (Real)op.a, op.b, pend, gsum);
+                    // lane-bit butterflies: position 3 (DPP), complex64 also position 4
+                    const int dl = L->dpp;
+                    if constexpr (sizeof(Real) == 8) {
+                        if (dl != 0)
+                            lane_round<kLaneX8, Real, R, NV>(vr, vi, op.flags, (Real)op.a, op.b, pend, gsum);
+                    } else if constexpr (T == 14) {
+                        if (dl & 8)
+                            lane_round<kLaneX8, Real, R, NV>(vr, vi, op.flags, (Real)op.a, op.b, pend, gsum);
+                        else if (dl & 16)
+                            lane_round<kLaneX16, Real, R, NV>(vr, vi, op.flags, (Real)op.a, op.b, pend, gsum);
+                    } else {
+                        // 13-bit complex64 tiles (adjoint programs) plan lane position 3 only
+                        if (dl != 0)
+                            lane_round<kLaneX8, Real, R, NV>(vr, vi, op.flags, (Real)op.a, op.b, pend, gsum);
+                    }
                 };
                 if constexpr (KC > 0) {
 #pragma unroll
@@ -780,7 +851,9 @@ static int run_pass(const PassArgs& a, void* stream) {
     } else if (a.lut_half >= 0) {
         hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, true, true, 0>), grid, block, 0, st, a);
     } else {
-        hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, true, false, 0>), grid, block, 0, st, a);
+        // real-valued instances: FP64 sincos per thread needs more registers;
+        // one workgroup per CU lets the compiler keep them in the AGPR half
+        hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, 1, true, false, 0>), grid, block, 0, st, a);
     }
     return (int)hipGetLastError();
 }

@@ -147,12 +147,16 @@ def test_plan_covers_every_qubit_once(sv, dtype, n):
             # tile bit -> global bit
             glob = [l if l < c else lo + (l - c) for l in active]
             covered += glob if gi > 0 else [l for l in active]
-            # blocks: every active bit is butterflied exactly once in each direction
+            # blocks: every active bit is butterflied exactly once in each direction,
+            # either as a register slot or as a cross-lane pair (lane position 3 or 4)
             for direction in ("fwd", "bwd"):
                 seen = []
                 for blk in g["blocks"]:
                     m = blk[direction]
                     seen += [blk["bits"][k] for k in range(R) if m >> k & 1]
+                    tb = [l for l in range(T) if l not in blk["bits"]]
+                    assert blk["dpp"] in (0, 8, 16)
+                    seen += [tb[q] for q in range(6) if blk["dpp"] >> q & 1]
                 assert sorted(seen) == active
             # the first layout leaves tile bits 0..5 as lane bits (coalesced loads)
             if n >= T and len(g["blocks"]) > 1:

@@ -243,6 +243,40 @@ def test_group_orders_agree(sv, orc, dtype):
     assert np.max(np.abs(g1[2] - g0[2])) <= GRAD_TOL[dtype] * scale
 
 
+@pytest.mark.parametrize("dtype,n", [("c128", 23), ("c64", 24), ("c64", 9), ("c64", 16)])
+def test_lane_butterfly_plans(sv, orc, dtype, n):
+    """Plans that butterfly one qubit across lanes (instead of one more LDS
+    layout) against the oracle, for the forward state, the fused energy and the
+    adjoint gradient, and against the same run with that option off."""
+    plans = sv.describe(n, dtype)["plans"]
+    assert any(b["dpp"] for g in plans["nv1"] for b in g["blocks"])
+    p = 2
+    inst = instance_for(n, "int", 90 + n)
+    H = sv.Ising.from_instance(inst)
+    g, b = I.uniform_params(p, 91 + n, -1.0, 1.0)
+    E = orc.energies(inst)
+    ref = orc.qaoa_state(inst, g, b, E=E)
+    ro = orc.observables(inst, ref, E=E)
+    s = sv.State(n, dtype)
+    e = sv.qaoa_energy(s, H, g, b)
+    assert np.max(np.abs(s.to_numpy() - ref)) <= AMP_TOL[dtype]
+    assert abs(e[0] - ro[1]) <= energy_tol(orc, inst, ro[1])
+    psi, lam = sv.State(n, dtype), sv.State(n, dtype)
+    f, dg, db = sv.grad(psi, lam, H, g, b)
+    _, rg, rb = orc.grad_tangent(inst, g, b)
+    scale = max(np.max(np.abs(np.concatenate([rg, rb]))), orc.coeff_scale(inst))
+    assert np.max(np.abs(dg - rg)) <= GRAD_TOL[dtype] * scale
+    assert np.max(np.abs(db - rb)) <= GRAD_TOL[dtype] * scale
+    sv.tune_set("dpp", 0)
+    try:
+        assert not any(b["dpp"] for g in sv.describe(n, dtype)["plans"]["nv1"] for b in g["blocks"])
+        s0 = sv.State(n, dtype)
+        sv.qaoa_forward(s0, H, g, b)
+    finally:
+        sv.tune_set("dpp", 1)
+    assert np.max(np.abs(s0.to_numpy() - s.to_numpy())) <= AMP_TOL[dtype]
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_zero_angles_identity(sv, dtype):
     n = 17
