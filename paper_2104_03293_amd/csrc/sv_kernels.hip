@@ -234,14 +234,15 @@ __device__ __forceinline__ void lane_round(Real (&vr)[NV][1 << R], Real (&vi)[NV
     }
 #pragma unroll
     for (int v = 0; v < NV; v++) {
-        if (!(flags & (1 << v))) continue;
+        const bool mine = NV == 1 || (flags & (1 << v)) != 0;
+        const Real tv = mine ? t : (Real)0;
 #pragma unroll
         for (int r = 0; r < NR; r++) {
             const Real pr = lane_xor<CTRL>(vr[v][r]), pi = lane_xor<CTRL>(vi[v][r]);
-            vr[v][r] = fma(t, pi, vr[v][r]);
-            vi[v][r] = fma(-t, pr, vi[v][r]);
+            vr[v][r] = fma(tv, pi, vr[v][r]);
+            vi[v][r] = fma(-tv, pr, vi[v][r]);
         }
-        pend[v] *= cosb;
+        pend[v] *= mine ? cosb : 1.0;
     }
 }
 
@@ -276,14 +277,18 @@ __device__ __forceinline__ void mix_round(Real (&vr)[NV][1 << R], Real (&vi)[NV]
         }
 #pragma unroll
         for (int v = 0; v < NV; v++) {
-            if (!(flags & (1 << v))) continue;
+            // A vector the op does not touch runs identity butterflies (t = 0)
+            // instead of a branch, which would force register copies at the
+            // join.  One-vector passes always mix psi.
+            const bool mine = NV == 1 || (flags & (1 << v)) != 0;
+            const Real tv = mine ? tk : (Real)0;
 #pragma unroll
             for (int r = 0; r < NR; r++) {
                 if (r & (1 << k)) continue;
                 const int r2 = r | (1 << k);
-                butterfly<Real>(vr[v][r], vi[v][r], vr[v][r2], vi[v][r2], tk);
+                butterfly<Real>(vr[v][r], vi[v][r], vr[v][r2], vi[v][r2], tv);
             }
-            pend[v] *= on ? cosb : 1.0;
+            pend[v] *= (on && mine) ? cosb : 1.0;
         }
     }
 }
