@@ -300,6 +300,7 @@ struct Geometry {
     std::vector<std::vector<int>> blocks;  // register bit blocks per layout
     std::vector<uint32_t> act_fwd, act_bwd;
     std::vector<uint32_t> dpp;  // per layout: lane positions butterflied across lanes (bit 3 or 4)
+    bool pivot = true;          // layouts share tile bit T-1 in register slot R-1 (half-tile exchanges)
 };
 
 static uint32_t swizzle(uint32_t u, int G) {
@@ -320,8 +321,13 @@ static int swz_bits(sv_dtype d) { return d == SV_C128 ? 3 : 4; }
 // remaining active bits are covered from the top with blocks that start at or
 // above the swizzle width G, so the last layout again has the carriers as its
 // lowest lane bits (coalesced stores).
-static Geometry make_geometry(int n, int T, int R, int c, int lo, int g, int G, uint32_t lane_pos_mask) {
+// pivot: every layout keeps tile bit T - 1 in register slot R - 1, so that an
+// LDS exchange moves half a tile at a time (one-vector kernels, two
+// workgroups per CU); without it (two-vector kernels, one workgroup per CU
+// with a full-tile LDS buffer) all R register slots are free.
+static Geometry make_geometry(int n, int T, int R, int c, int lo, int g, int G, uint32_t lane_pos_mask, bool pivot) {
     Geometry geo{};
+    geo.pivot = pivot;
     geo.T = T;
     geo.R = R;
     geo.c = c;
@@ -339,7 +345,7 @@ static Geometry make_geometry(int n, int T, int R, int c, int lo, int g, int G, 
     } else {
         for (int l = c; l < T; l++) active |= 1u << l;
     }
-    const int F = R - 1;  // free (non-pivot) register slots
+    const int F = pivot ? R - 1 : R;  // free register slots of a block
     std::vector<std::vector<int>> blk;
     {
         std::vector<int> b0;
@@ -349,7 +355,7 @@ static Geometry make_geometry(int n, int T, int R, int c, int lo, int g, int G, 
     auto add = [&](int a) {
         std::vector<int> b;
         for (int l = a; l < a + F; l++) b.push_back(l);
-        b.push_back(T - 1);
+        if (pivot) b.push_back(T - 1);
         blk.push_back(b);
     };
     if (groupA) {
@@ -396,7 +402,7 @@ static Geometry make_geometry(int n, int T, int R, int c, int lo, int g, int G, 
         auto in = [](const std::vector<int>& v, int l) { return std::find(v.begin(), v.end(), l) != v.end(); };
         // pad a block to F free bits with bits that need no butterfly here
         auto pad = [&](std::vector<int>& b, int x, bool last) {
-            for (int l = T - 2; l >= 0 && (int)b.size() < F; l--) {
+            for (int l = pivot ? T - 2 : T - 1; l >= 0 && (int)b.size() < F; l--) {
                 if (in(b, l) || l == x || (last && l < nlow)) continue;
                 if ((active >> l & 1u) && !(b0 >> l & 1u)) continue;  // only inactive or first-layout bits
                 b.push_back(l);
@@ -418,7 +424,7 @@ static Geometry make_geometry(int n, int T, int R, int c, int lo, int g, int G, 
                 for (int q = 0; q < nv; q++) (sub >> q & 1u ? last : mid).push_back(V[q]);
                 if ((int)mid.size() > (m - 1) * F) continue;
                 if (!pad(last, x, true)) continue;
-                uint32_t lm = 1u << (T - 1);
+                uint32_t lm = pivot ? 1u << (T - 1) : 0u;
                 for (int l : last) lm |= 1u << l;
                 std::vector<int> tbits;
                 for (int l = 0; l < T; l++)
@@ -434,11 +440,11 @@ static Geometry make_geometry(int n, int T, int R, int c, int lo, int g, int G, 
                 for (size_t q = 0; q < mid.size() && good; q += F) {
                     std::vector<int> b(mid.begin() + q, mid.begin() + std::min(mid.size(), q + F));
                     good = pad(b, x, false);
-                    b.push_back(T - 1);
+                    if (pivot) b.push_back(T - 1);
                     nb.push_back(b);
                 }
                 if (!good) continue;
-                last.push_back(T - 1);
+                if (pivot) last.push_back(T - 1);
                 nb.push_back(last);
                 keep = nb;
                 dpp.assign(keep.size(), 0u);
@@ -477,21 +483,25 @@ static Geometry make_geometry(int n, int T, int R, int c, int lo, int g, int G, 
 static std::vector<Geometry> plan_groups(int n, sv_dtype dt, int nv, bool grad = false) {
     const Shape sh = shape_for((int)dt, nv, grad);
     const int T = sh.T, R = sh.R, G = swz_bits(dt);
-    // lane positions the kernels butterfly across lanes: 3 (all tiles), 4 (14-bit complex64 tiles)
-    const uint32_t dpp = knob_for("dpp", (int)dt, n) == 0 ? 0u : (dt == SV_C64 && T == 14 ? 0x18u : 0x8u);
+    // lane positions the one-vector kernels butterfly across lanes: 3, and 4 for
+    // 14-bit complex64 tiles.  Two-vector passes keep every qubit in registers:
+    // their lane butterflies would cost six cross-lane moves per amplitude
+    // (both vectors and the gradient pair term), more than the exchange saved.
+    const bool pos4 = dt == SV_C64 && T == 14;
+    const uint32_t dpp = (knob_for("dpp", (int)dt, n) == 0 || nv == 2) ? 0u : (pos4 ? 0x18u : 0x8u);
     std::vector<Geometry> out;
     if (n <= T) {
-        out.push_back(make_geometry(n, T, R, n, n, 0, G, dpp));
+        out.push_back(make_geometry(n, T, R, n, n, 0, G, dpp, nv == 1));
         return out;
     }
-    out.push_back(make_geometry(n, T, R, T, T, 0, G, dpp));
+    out.push_back(make_geometry(n, T, R, T, T, 0, G, dpp, nv == 1));
     const int cmin = std::max(G, knob_for(dt == SV_C128 ? "cmin128" : "cmin64", (int)dt, n));
     const int rest = n - T, gmax = T - cmin;
     const int ng = (rest + gmax - 1) / gmax;
     int lo = T;
     for (int i = 0; i < ng; i++) {
         int g = rest / ng + (i < rest % ng ? 1 : 0);
-        out.push_back(make_geometry(n, T, R, T - g, lo, g, G, dpp));
+        out.push_back(make_geometry(n, T, R, T - g, lo, g, G, dpp, nv == 1));
         lo += g;
     }
     return out;
@@ -545,7 +555,8 @@ static int build_geobuf(const Geometry& geo, const sv_ising_s* H, sv_dtype dt, G
             for (int k = 0; k < R; k++)
                 if (r >> k & 1) u |= 1u << rb[k];
             L.reg_u[r] = u;
-            L.reg_lds[r] = swizzle(u & ((1u << (T - 1)) - 1u), G) * (uint32_t)elem_size(dt);
+            const uint32_t um = geo.pivot ? (u & ((1u << (T - 1)) - 1u)) : u;  // half-tile slots drop the pivot
+            L.reg_lds[r] = swizzle(um, G) * (uint32_t)elem_size(dt);
             L.reg_goff[r] = (u & geo.phantom) ? 0 : gmap(u);
         }
         L.thr_off = 0;
@@ -604,6 +615,7 @@ static int get_geobuf(const Geometry& geo, sv_ising_s* H, sv_dtype dt, GeoBuf** 
         for (int l : geo.blocks[j]) mix((uint64_t)l);
         mix(1000u + geo.dpp[j]);
     }
+    mix(geo.pivot ? 7u : 9u);
     GeoKey key{geo.T, geo.R, geo.c, geo.lo, geo.g, geo.n, (int)dt, sig};
     if (H) {
         std::lock_guard<std::mutex> g(H->mu);

@@ -328,7 +328,11 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
     constexpr int NW = NT / 64;
     constexpr int G = (sizeof(Real) == 8) ? 3 : 4;
 
-    __shared__ V2 xbuf[1 << (T - 1)];
+    // one-vector kernels exchange half a tile at a time (pivot layouts, two
+    // workgroups per CU); two-vector kernels run one workgroup per CU (register
+    // bound) and exchange whole tiles.
+    constexpr bool FULLX = NV == 2;
+    __shared__ V2 xbuf[FULLX ? (1 << T) : (1 << (T - 1))];
     __shared__ double s_g[kTF];  // tile fields g_l and E_fixed (entry kTF - 1)
     __shared__ double s_red[NW][NS];
 
@@ -440,7 +444,8 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                 auto round = [&](int step) {
                     const int j = fwd ? step : (K - 1 - step);
                     if (step > 0) {
-                        // LDS exchange cur -> j in two halves (pivot register slot R-1)
+                        // LDS exchange cur -> j: in two halves split by the pivot (register
+                        // slot R-1) for one vector, as whole tiles for two vectors
                         const GeoLayout* Lt = &geo->L[j];
                         const uint32_t new_u = thread_index_bits<T - R>(t, Lt->tmask);
                         // byte offsets: one XOR with the table entry per access
@@ -449,12 +454,14 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                         char* xb = reinterpret_cast<char*>(xbuf);
 #pragma unroll
                         for (int v = 0; v < NV; v++) {
+                            constexpr int NHALF = FULLX ? 1 : 2;
+                            constexpr int NQ = FULLX ? NR : NH;
 #pragma unroll
-                            for (int h = 0; h < 2; h++) {
+                            for (int h = 0; h < NHALF; h++) {
                                 __syncthreads();
 #pragma unroll
-                                for (int q = 0; q < NH; q++) {
-                                    const int r = h * NH + q;
+                                for (int q = 0; q < NQ; q++) {
+                                    const int r = h * NQ + q;
                                     V2 x;
                                     x.x = vr[v][r];
                                     x.y = vi[v][r];
@@ -462,8 +469,8 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                                 }
                                 __syncthreads();
 #pragma unroll
-                                for (int q = 0; q < NH; q++) {
-                                    const int r = h * NH + q;
+                                for (int q = 0; q < NQ; q++) {
+                                    const int r = h * NQ + q;
                                     const V2 x = *reinterpret_cast<const V2*>(xb + (dst ^ Lt->reg_lds[r]));
                                     vr[v][r] = x.x;
                                     vi[v][r] = x.y;
@@ -477,9 +484,13 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                     }
                     const int act = fwd ? L->act_fwd : L->act_bwd;
                     mix_round<Real, R, NV>(vr, vi, act, op.flags, (Real)op.a, op.b, pend, gsum);
-                    // lane-bit butterflies: position 3 (DPP), complex64 also position 4
+                    // lane-bit butterflies (one-vector kernels): position 3 (DPP);
+                    // position 4 (swizzle) for 14-bit complex64 tiles (a second branch
+                    // in the complex128 kernel would exhaust its registers)
                     const int dl = L->dpp;
-                    if constexpr (sizeof(Real) == 8) {
+                    if constexpr (NV == 2) {
+                        (void)dl;  // two-vector plans butterfly every qubit in registers
+                    } else if constexpr (sizeof(Real) == 8) {
                         if (dl != 0)
                             lane_round<kLaneX8, Real, R, NV>(vr, vi, op.flags, (Real)op.a, op.b, pend, gsum);
                     } else if constexpr (T == 14) {
