@@ -257,6 +257,44 @@ def grad_fd(inst, gamma, beta, h=1e-4, E=None):
     return dg, db
 
 
+# ----------------------------------------------------------------------------- product states
+def product_state_factors(h, gamma, beta) -> np.ndarray:
+    """Single-qubit factors of the QAOA state when all couplings vanish (Eq. HC
+    with J = 0): H_C = sum_i h_i s_i separates, so every layer of Eq. QAOA_state
+    acts on each qubit alone and the state is the tensor product of
+    phi_i = prod_k exp(-i beta_k X) exp(-i gamma_k h_i s) |+>, s = -1 for bit 0
+    and +1 for bit 1 (Sec. III.A.3).  Returns phi[i, b], shape (n, 2)."""
+    h = np.asarray(h, dtype=np.float64)
+    phi = np.full((len(h), 2), 1.0 / math.sqrt(2.0), dtype=np.complex128)
+    for g, b in zip(np.atleast_1d(gamma), np.atleast_1d(beta)):
+        phi[:, 0] *= np.exp(1j * g * h)    # s = -1: exp(-i g h (-1))
+        phi[:, 1] *= np.exp(-1j * g * h)   # s = +1
+        c, sn = math.cos(b), math.sin(b)
+        a0, a1 = phi[:, 0].copy(), phi[:, 1].copy()
+        phi[:, 0] = c * a0 - 1j * sn * a1  # exp(-i b X) = c - i s X
+        phi[:, 1] = c * a1 - 1j * sn * a0
+    return phi
+
+
+def product_amplitudes(h, gamma, beta, zs) -> np.ndarray:
+    """Amplitudes psi(z) = prod_i phi_i[bit_i(z)] of the J = 0 state at the
+    basis indices zs (any n, no state vector)."""
+    phi = product_state_factors(h, gamma, beta)
+    zs = np.asarray(zs, dtype=np.uint64)
+    out = np.ones(len(zs), dtype=np.complex128)
+    for i in range(phi.shape[0]):
+        bit = ((zs >> np.uint64(i)) & np.uint64(1)).astype(np.int64)
+        out *= phi[i, bit]
+    return out
+
+
+def product_energy(h, gamma, beta) -> float:
+    """<H_C> = sum_i h_i (|phi_i[1]|^2 - |phi_i[0]|^2) of the J = 0 state."""
+    phi = product_state_factors(h, gamma, beta)
+    pz = np.abs(phi[:, 1]) ** 2 - np.abs(phi[:, 0]) ** 2
+    return float(np.sum(np.asarray(h, dtype=np.float64) * pz))
+
+
 # ----------------------------------------------------------------------------- schedules
 def aqa_linear_schedule(steps: int, tau: float, paper_sign: bool = True):
     """Coarse first-order annealing steps with A(s) = 1 - s, B(s) = s (a linear

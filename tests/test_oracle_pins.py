@@ -249,6 +249,23 @@ def test_product_state_closed_form(orc):
     assert abs(en - np.sum(inst["h"] * np.sin(2 * g * inst["h"])) * math.sin(2 * b)) < 1e-13
 
 
+@pytest.mark.parametrize("p", [1, 3])
+def test_product_state_factors_vs_full_state(orc, p):
+    # The factorised J = 0 state (used for sampled checks at sizes no state
+    # vector fits) against the bit-loop oracle's full state and energy.
+    n = 10
+    inst = I.fields_only(n, 6 + p)
+    rng = np.random.default_rng(60 + p)
+    g, b = rng.uniform(-1.2, 1.2, p), rng.uniform(-1.2, 1.2, p)
+    psi = orc.qaoa_state(inst, g, b)
+    amp = orc.product_amplitudes(inst["h"], g, b, np.arange(1 << n))
+    assert np.max(np.abs(psi - amp)) < 1e-14
+    assert abs(orc.observables(inst, psi)[1] - orc.product_energy(inst["h"], g, b)) < 1e-13
+    if p == 1:  # and the p = 1 closed form sum_i h_i sin(2 g h_i) sin(2 b)
+        ref = np.sum(inst["h"] * np.sin(2 * g[0] * inst["h"])) * math.sin(2 * b[0])
+        assert abs(orc.product_energy(inst["h"], g, b) - ref) < 1e-13
+
+
 def test_spin_z_against_dense(orc):
     inst = I.regular3_pm1(8, 3)
     psi = orc.qaoa_state(inst, [0.5, 1.0], [0.4, -0.2])
