@@ -55,6 +55,7 @@ std::map<std::string, int> g_knobs = {
     {"stagger", 0},   // persistent grids: start delay of the second half (units of 64*127 clocks)
     {"snake", 1},     // 1: the contiguous tile group takes a middle slot of the layer's group order
     {"dpp", 1},       // 1: one active bit may be butterflied across lanes to save a layout
+    {"ldsswz", 4},    // LDS slot swizzle width of the tile passes (3..5)
 };
 int knob(const char* k) {
     std::lock_guard<std::mutex> g(g_knob_mu);
@@ -121,6 +122,7 @@ extern "C" int sv_tune_set(const char* name, int value) {
         return fail(SV_ERR_ARG, "%s must be in [0, 8]", name);
     if (std::string(name) == "ntmin" && (value < 0 || value > 64)) return fail(SV_ERR_ARG, "ntmin must be in [0, 64]");
     if (std::string(name) == "persist" && (value < 0 || value > 8)) return fail(SV_ERR_ARG, "persist must be in [0, 8]");
+    if (std::string(name) == "ldsswz" && (value < 3 || value > 5)) return fail(SV_ERR_ARG, "ldsswz must be in [3, 5]");
     if ((std::string(name) == "snake" || std::string(name) == "dpp") && (value < 0 || value > 1))
         return fail(SV_ERR_ARG, "%s must be 0 or 1", name);
     if (std::string(name) == "stagger" && (value < 0 || value > 64)) return fail(SV_ERR_ARG, "stagger must be in [0, 64]");
@@ -312,7 +314,13 @@ static uint32_t swizzle(uint32_t u, int G) {
     return u ^ (f & ((1u << G) - 1u));
 }
 
-static int swz_bits(sv_dtype d) { return d == SV_C128 ? 3 : 4; }
+static int swz_bits(sv_dtype d) { return d == SV_C128 ? 3 : 4; }  // planning: lowest lane bits of a 128-B run
+// LDS slot swizzle width of the tile passes: the high tile bits are folded into
+// the low 4 slot bits.  With 16 lanes served per LDS cycle for 16-B elements
+// this keeps every complex128 exchange of every plan conflict-free (checked by
+// replaying the plans); 3 bits left the contiguous group's second layout
+// two-way conflicted (measured as LDS bank-conflict cycles).
+static int lds_swz_bits(sv_dtype d, int n) { return knob_for("ldsswz", (int)d, n); }
 
 // Register-bit blocks for a geometry.  Every block keeps the pivot (tile bit
 // T-1) in register slot R-1 so that an LDS exchange runs in two halves.  The
@@ -517,7 +525,7 @@ static int global_bit(const Geometry& geo, int l) {
 static int build_geobuf(const Geometry& geo, const sv_ising_s* H, sv_dtype dt, GeoBuf** out) {
     GeoBuf hb;
     memset(&hb, 0, sizeof(hb));
-    const int T = geo.T, R = geo.R, G = swz_bits(dt);
+    const int T = geo.T, R = geo.R, G = lds_swz_bits(dt, geo.n);
     const int NTB = T - R, NT = 1 << NTB;
     if (T >= kTF) return fail(SV_ERR_UNSUPPORTED, "internal: tile of %d bits exceeds the field table", T);
     std::vector<int> inv(64, -1);  // global bit -> tile bit
@@ -616,6 +624,7 @@ static int get_geobuf(const Geometry& geo, sv_ising_s* H, sv_dtype dt, GeoBuf** 
         mix(1000u + geo.dpp[j]);
     }
     mix(geo.pivot ? 7u : 9u);
+    mix(100u + (uint64_t)lds_swz_bits(dt, geo.n));
     GeoKey key{geo.T, geo.R, geo.c, geo.lo, geo.g, geo.n, (int)dt, sig};
     if (H) {
         std::lock_guard<std::mutex> g(H->mu);
@@ -1023,6 +1032,7 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         a.nops = 0;
         a.need_e = 0;
         a.nt = (geo.phantom == 0 && geo.c >= ntmin) ? 3 : 0;
+        a.swz = lds_swz_bits(s->dt, s->n);
         a.grid = persist * ncu;
         a.stagger = stagger;
         for (const Op& op : p.ops) {

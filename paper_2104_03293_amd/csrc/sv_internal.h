@@ -133,6 +133,7 @@ struct PassArgs {
     int32_t nops;           // informational; ops[i].kind == 0 marks an absent slot
     int32_t need_e;         // the POINT op evaluates E (tile fields needed)
     int32_t nt;             // 3: nontemporal loads and stores (long contiguous runs), 0: plain
+    int32_t swz;            // LDS slot swizzle width (the geometry tables use the same)
     int32_t grid;           // workgroups launched (< ntiles: persistent grid-stride walk), 0: one per tile
     int32_t stagger;        // persistent grids: start delay of the second half, in units of s_sleep(127)
     int32_t nphase;

@@ -326,7 +326,6 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
     constexpr int NR = 1 << R;
     constexpr int NH = NR / 2;  // registers per pivot half
     constexpr int NW = NT / 64;
-    constexpr int G = (sizeof(Real) == 8) ? 3 : 4;
 
     // one-vector kernels exchange half a tile at a time (pivot layouts, two
     // workgroups per CU); two-vector kernels run one workgroup per CU (register
@@ -449,8 +448,8 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                         const GeoLayout* Lt = &geo->L[j];
                         const uint32_t new_u = thread_index_bits<T - R>(t, Lt->tmask);
                         // byte offsets: one XOR with the table entry per access
-                        const uint32_t src = lds_swizzle(thr_u, G) * (uint32_t)sizeof(V2);
-                        const uint32_t dst = lds_swizzle(new_u, G) * (uint32_t)sizeof(V2);
+                        const uint32_t src = lds_swizzle(thr_u, a.swz) * (uint32_t)sizeof(V2);
+                        const uint32_t dst = lds_swizzle(new_u, a.swz) * (uint32_t)sizeof(V2);
                         char* xb = reinterpret_cast<char*>(xbuf);
 #pragma unroll
                         for (int v = 0; v < NV; v++) {

@@ -68,7 +68,7 @@ def replay(n, g, G):
 @pytest.mark.parametrize("n", [1, 2, 4, 7, 9, 12, 13, 14, 15, 16, 19, 21, 24])
 def test_every_layout_is_a_bijection(sv, dtype, n):
     d = sv.describe(n, dtype)
-    G = 3 if dtype == "c128" else 4
+    G = 4  # LDS swizzle width of the tile passes
     for key in ("nv1", "grad_nv1", "grad_nv2"):
         for g in d["plans"][key]:
             replay(n, g, G)
@@ -90,3 +90,39 @@ def test_large_plans_in_bounds(sv, dtype, n):
             base = ((w & ((1 << nlow) - 1)) << c) | ((w >> nlow) << (lo + gb))
             top = base | ((1 << c) - 1) | (((1 << gb) - 1) << lo)
             assert top == (1 << n) - 1
+
+
+def bank_extra_cycles(g, G, lanes_per_cycle, pivot):
+    """Extra LDS cycles of one exchange write/read over all registers of every
+    layout, when `lanes_per_cycle` consecutive lanes are served together and a
+    cycle covers that many consecutive element slots (modulo)."""
+    T, R = g["T"], g["R"]
+    extra = 0
+    for blk in g["blocks"]:
+        rb = blk["bits"]
+        tb = [l for l in range(T) if l not in rb]
+        regs = range(1 << (R - 1)) if pivot else range(1 << R)
+        lane = np.arange(64)
+        thr = np.zeros(64, dtype=np.int64)
+        for j in range(6):
+            thr |= ((lane >> j) & 1) << tb[j]
+        for r in regs:
+            ru = sum(((r >> k) & 1) << rb[k] for k in range(R))
+            u = thr | ru
+            if pivot:
+                u &= (1 << (T - 1)) - 1
+            slot = swizzle(u, G) % lanes_per_cycle
+            for w0 in range(0, 64, lanes_per_cycle):
+                extra += np.bincount(slot[w0:w0 + lanes_per_cycle], minlength=lanes_per_cycle).max() - 1
+    return int(extra)
+
+
+@pytest.mark.parametrize("n", [14, 20, 23, 26, 30, 32, 33])
+def test_complex128_exchanges_conflict_free(sv, n):
+    """Every complex128 exchange slot pattern is free of LDS bank conflicts
+    whether 8 or 16 lanes of 16-B elements are served per cycle."""
+    d = sv.describe(n, "c128")
+    for key in ("nv1", "grad_nv1", "grad_nv2"):
+        for g in d["plans"][key]:
+            for lanes in (8, 16):
+                assert bank_extra_cycles(g, 4, lanes, key != "grad_nv2") == 0, (key, g["c"], lanes)
