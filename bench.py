@@ -109,8 +109,9 @@ def main():
     avg_ms = k["ms"] / max(1, k["launches"])
     avg_bytes = k["bytes"] / max(1, k["launches"])
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    traffic = committed_traffic(args.dtype, n, p)
     roof = {"bound": "hbm", "kernel": f"k_pass<{args.dtype}>", "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "launches_per_step": k["launches"] / args.steps, "avg_launch_ms": round(avg_ms, 4),
             "algorithmic_bytes_per_launch": avg_bytes}
 
@@ -170,6 +171,26 @@ def main():
         "extras": extras,
     }
     print(json.dumps(res), flush=True)
+
+
+def committed_traffic(dtype: str, n: int, p: int):
+    """HBM bytes per tile-pass launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary of this workload, or None when there is none or the
+    kernel source changed since the counters were taken."""
+    import hashlib
+    import re
+
+    f = ROOT / "profiles" / f"k_pass_{dtype}_traffic_n{n}_p{p}.md"
+    if not f.exists():
+        return None
+    text = f.read_text()
+    src = ROOT / "paper_2104_03293_amd" / "csrc" / "sv_kernels.hip"
+    sha = hashlib.sha256(src.read_bytes()).hexdigest()
+    m = re.search(r"kernel source sha256: ([0-9a-f]{64})", text)
+    t = re.search(r"traffic_bytes_per_launch: ([0-9.eE+]+)", text)
+    if not m or not t or m.group(1) != sha:
+        return None
+    return float(t.group(1))
 
 
 def cpu_baseline(n: int, p: int):
