@@ -146,6 +146,23 @@ def main():
                          "energy_diff_vs_c128": abs(o64[0] - out[0])}
         log(f"[bench] c64 {ms64:.3f} ms/step")
         del s64
+        # dense exact-cover-structured instance (F = 472 columns, half-integer
+        # couplings between every pair of overlapping rows), rescaled angles
+        a = I.exact_cover_matrix(n, 472, 4 + n)
+        Hx, Cx = sv.Ising.exact_cover(a)
+        rx = sv.rescale_factor(Hx)
+        sv.ground(Hx)
+        sv.qaoa_energy(s, Hx, gam / rx, bet)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ox = sv.qaoa_energy(s, Hx, gam / rx, bet)
+        torch.cuda.synchronize()
+        msx = (time.perf_counter() - t0) * 1e3 / args.steps
+        extras["exact_cover"] = {"ms_per_step": round(msx, 3), "amp_updates_per_s": updates / (msx * 1e-3),
+                                 "couplings": int(np.count_nonzero(np.triu(a.astype(np.int64) @ a.T.astype(np.int64), 1))),
+                                 "rescale_r": rx, "energy_plus_C": ox[0] * 1.0 + Cx, "p_gs": ox[1]}
+        log(f"[bench] exact cover {msx:.3f} ms/step")
 
     cpu = None
     if not args.no_extras:

@@ -101,6 +101,21 @@ int sv_ising_create(int n, const double* h, int m, const int32_t* ei, const int3
                     const double* J, sv_ising* out);
 int sv_ising_free(sv_ising H);
 
+/* Exact cover instance (Sec. III.A.3): the Boolean problem matrix a
+ * (nrows x ncols, row-major, entries 0/1) of sum_f (sum_i a_if x_i - 1)^2
+ * becomes, with x_i = (1 + s_i)/2 (Eq. xtosigma), the Ising instance of
+ * Eqs. HChi and HCJij (h_i = sum_j (a a^T)_ij / 2 - (a b)_i, J_ij =
+ * (a a^T)_ij / 2 for every pair with a nonzero overlap) plus the constant C
+ * of Eq. HCC, returned in *constant (may be NULL): E(z) + C is the objective.
+ * nrows = qubits (1..34), ncols >= 1; entries other than 0/1 are an error
+ * (SV_ERR_ARG).  The half-integer coefficients use the phase tables. */
+int sv_ising_exact_cover(int nrows, int ncols, const uint8_t* a, double* constant, sv_ising* out);
+
+/* r of Eq. rescale for an instance: max of max(h)/2, min(h)/(-2), max(J)/1,
+ * min(J)/(-1) and 0.  Dividing h, J and C by r does not change the solutions;
+ * callers apply it as gamma / r and <H_C> * r (the state depends only on gamma E). */
+int sv_rescale_factor(sv_ising H, double* r);
+
 /* Brute-force ground state over all 2^n basis states (the full-enumeration
  * search of Sec. III.C.2, Table III): minimum energy, number of basis states
  * at that energy and the smallest such index.  Energies of instances whose

@@ -257,6 +257,44 @@ def grad_fd(inst, gamma, beta, h=1e-4, E=None):
     return dg, db
 
 
+# ----------------------------------------------------------------------------- exact cover
+def exact_cover_ising(a):
+    """Ising form of the exact cover objective sum_f (sum_i a_if x_i - 1)^2 with
+    x_i = (1 + s_i)/2 (Eqs. exactcover, xtosigma): h_i = sum_j (a a^T)_ij / 2
+    - (a b)_i, J_ij = (a a^T)_ij / 2 for i < j (Eqs. HChi, HCJij) and
+    C = b^T b + sum_{i<j} (a a^T)_ij / 2 + sum_i ((a a^T)_ii - 2 (a b)_i) / 2
+    (Eq. HCC), b = ones(F).  Returns (instance dict with the nonzero J_ij, C)."""
+    a = np.asarray(a, dtype=np.int64)
+    nr, nc = a.shape
+    A = a @ a.T
+    ab = a.sum(axis=1)
+    h = 0.5 * A.sum(axis=1) - ab
+    iu, ju = np.triu_indices(nr, k=1)
+    Jall = 0.5 * A[iu, ju]
+    keep = Jall != 0
+    C = float(nc) + 0.5 * float(A[iu, ju].sum()) + 0.5 * float(np.sum(np.diag(A) - 2 * ab))
+    inst = {"n": int(nr), "h": h.astype(np.float64), "ei": iu[keep].astype(np.int32),
+            "ej": ju[keep].astype(np.int32), "J": Jall[keep].astype(np.float64)}
+    return inst, C
+
+
+def exact_cover_objective(a, z: int) -> int:
+    """sum_f (sum_i a_if x_i - 1)^2 for the assignment x_i = bit i of z."""
+    a = np.asarray(a, dtype=np.int64)
+    x = (int(z) >> np.arange(a.shape[0])) & 1
+    return int(np.sum((x @ a - 1) ** 2))
+
+
+def rescale_factor(inst, hmax=2.0, jmax=1.0) -> float:
+    """r of Eq. rescale with h_max = -h_min = 2 and J_max = -J_min = 1."""
+    h = np.asarray(inst["h"], dtype=np.float64)
+    J = np.asarray(inst["J"], dtype=np.float64)
+    cands = [max(h.max() / hmax, 0.0), max(h.min() / -hmax, 0.0)]
+    if len(J):
+        cands += [max(J.max() / jmax, 0.0), max(J.min() / -jmax, 0.0)]
+    return float(max(cands))
+
+
 # ----------------------------------------------------------------------------- product states
 def product_state_factors(h, gamma, beta) -> np.ndarray:
     """Single-qubit factors of the QAOA state when all couplings vanish (Eq. HC

@@ -256,9 +256,10 @@ struct sv_ising_s {
     int n = 0, m = 0;
     std::vector<double> h, J;
     std::vector<int32_t> ei, ej;
-    bool integer = true;
+    bool integer = true;  // h, J integral
+    int qden = 0;         // smallest q in {1, 2, 4} with q h, q J integral (0: none): E on the grid Z / q
     double scale = 0.0;
-    int lut_half = -1;  // max(sum|h|+sum|J|, 2 max_k(|h_k| + sum_j |J_kj|)) for integer instances
+    int lut_half = -1;    // q * max(sum|h|+sum|J|, 2 max_k(|h_k| + sum_j |J_kj|)) when qden > 0
     // device tables
     double* d_h = nullptr;
     int32_t* d_adj_ptr = nullptr;
@@ -921,7 +922,8 @@ static int get_tf(sv_ising_s* H, const Geometry& geo, const GeoBuf* gb, hipStrea
     return SV_OK;
 }
 
-static double ground_tol(const sv_ising_s* H) { return H->integer ? 0.0 : 1e-9 * std::max(1.0, H->scale); }
+// Energies on a grid Z / q are computed exactly in FP64, so the ground set compares exactly.
+static double ground_tol(const sv_ising_s* H) { return H->qden > 0 ? 0.0 : 1e-9 * std::max(1.0, H->scale); }
 
 static int run_ground(sv_ising_s* H, hipStream_t stream);
 
@@ -980,6 +982,7 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
             j.Q = gb->L[ph.first].Q;  // device address inside the geometry table
             j.nr = 1 << geo.R;
             j.L = lut_half;
+            j.qinv = H && H->qden > 0 ? 1.0 / H->qden : 1.0;
             j.qph_off = (uint32_t)tab_need;
             tab_need += j.nr;
             j.lut_off = (uint32_t)tab_need;
@@ -1047,6 +1050,7 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         a.nphase = (int)p.phase.size();
         a.ptab = s->w.d_tab;
         a.lut_half = lut_half;
+        a.lut_q = H && H->qden > 0 ? (double)H->qden : 1.0;
         for (int q = 0; q < a.nphase; q++) {
             a.qph_off[q] = offs[pi][q].first;
             a.lut_off[q] = offs[pi][q].second;
@@ -1213,15 +1217,22 @@ extern "C" int sv_ising_create(int n, const double* h, int m, const int32_t* ei,
         H->ej.assign(ej, ej + m);
         H->J.assign(J, J + m);
     }
-    for (double v : H->h) {
-        H->integer = H->integer && v == std::round(v);
-        H->scale += std::fabs(v);
+    for (double v : H->h) H->scale += std::fabs(v);
+    for (double v : H->J) H->scale += std::fabs(v);
+    // Coefficients on a grid Z / q (integers, or the half-integers of exact
+    // cover instances, Eqs. HChi-HCJij) give energies on that grid: the phase
+    // factors then come from a table of exp(-i gamma m / q).
+    for (int q : {1, 2, 4}) {
+        bool ok = true;
+        for (double v : H->h) ok = ok && q * v == std::round(q * v);
+        for (double v : H->J) ok = ok && q * v == std::round(q * v);
+        if (ok) {
+            H->qden = q;
+            break;
+        }
     }
-    for (double v : H->J) {
-        H->integer = H->integer && v == std::round(v);
-        H->scale += std::fabs(v);
-    }
-    if (H->integer) {
+    H->integer = H->qden == 1;
+    if (H->qden > 0) {
         std::vector<double> loc(n, 0.0);
         for (int i = 0; i < n; i++) loc[i] = std::fabs(H->h[i]);
         for (int k = 0; k < m; k++) {
@@ -1230,7 +1241,8 @@ extern "C" int sv_ising_create(int n, const double* h, int m, const int32_t* ei,
         }
         double L = H->scale;
         for (double v : loc) L = std::max(L, 2.0 * v);
-        if (L <= 4096.0) H->lut_half = (int)L;
+        L *= H->qden;
+        if (L <= 65536.0) H->lut_half = (int)std::ceil(L);
     }
     // CSR adjacency over both endpoints
     std::vector<int32_t> ptr(n + 1, 0), nbr(2 * m);
@@ -1267,6 +1279,54 @@ extern "C" int sv_ising_create(int n, const double* h, int m, const int32_t* ei,
         return fail(e == hipErrorOutOfMemory ? SV_ERR_OOM : SV_ERR_HIP, "sv_ising_create: %s", hipGetErrorString(e));
     }
     *out = H;
+    return SV_OK;
+}
+
+extern "C" int sv_ising_exact_cover(int nrows, int ncols, const uint8_t* a, double* constant, sv_ising* out) {
+    if (!a || !out) return fail(SV_ERR_ARG, "sv_ising_exact_cover: NULL argument");
+    if (nrows < 1 || nrows > 34) return fail(SV_ERR_ARG, "sv_ising_exact_cover: nrows = %d outside [1, 34]", nrows);
+    if (ncols < 1) return fail(SV_ERR_ARG, "sv_ising_exact_cover: ncols = %d", ncols);
+    for (size_t k = 0; k < (size_t)nrows * ncols; k++)
+        if (a[k] > 1) return fail(SV_ERR_ARG, "sv_ising_exact_cover: entry %zu is %d, not 0/1", k, (int)a[k]);
+    // overlaps (a a^T)_ij and row counts (a b)_i
+    std::vector<int64_t> ov((size_t)nrows * nrows, 0), cnt(nrows, 0);
+    for (int i = 0; i < nrows; i++)
+        for (int f = 0; f < ncols; f++) cnt[i] += a[(size_t)i * ncols + f];
+    for (int i = 0; i < nrows; i++)
+        for (int j = i; j < nrows; j++) {
+            int64_t o = 0;
+            for (int f = 0; f < ncols; f++) o += a[(size_t)i * ncols + f] & a[(size_t)j * ncols + f];
+            ov[(size_t)i * nrows + j] = ov[(size_t)j * nrows + i] = o;
+        }
+    std::vector<double> h(nrows), J;
+    std::vector<int32_t> ei, ej;
+    int64_t off = 0, diag = 0, cnt_sum = 0;
+    for (int i = 0; i < nrows; i++) {
+        int64_t row = 0;
+        for (int j = 0; j < nrows; j++) row += ov[(size_t)i * nrows + j];
+        h[i] = 0.5 * (double)row - (double)cnt[i];  // Eq. HChi
+        diag += ov[(size_t)i * nrows + i];
+        cnt_sum += cnt[i];
+        for (int j = i + 1; j < nrows; j++) {
+            const int64_t o = ov[(size_t)i * nrows + j];
+            off += o;
+            if (o == 0) continue;
+            ei.push_back(i);
+            ej.push_back(j);
+            J.push_back(0.5 * (double)o);  // Eq. HCJij
+        }
+    }
+    // Eq. HCC: C = b^T b + sum_{i<j} (aa^T)_ij / 2 + sum_i ((aa^T)_ii - 2 (ab)_i) / 2
+    if (constant) *constant = (double)ncols + 0.5 * (double)off + 0.5 * (double)(diag - 2 * cnt_sum);
+    return sv_ising_create(nrows, h.data(), (int)J.size(), ei.data(), ej.data(), J.data(), out);
+}
+
+extern "C" int sv_rescale_factor(sv_ising H, double* r) {
+    if (!H || !r) return fail(SV_ERR_ARG, "sv_rescale_factor: NULL argument");
+    double v = 0.0;
+    for (double x : H->h) v = std::max({v, x / 2.0, x / -2.0});
+    for (double x : H->J) v = std::max({v, x / 1.0, x / -1.0});
+    *r = v;
     return SV_OK;
 }
 

@@ -111,7 +111,8 @@ struct TableJob {
     double gamma;
     const double* Q;        // device: the layout's Q[64]
     int32_t nr;             // registers per thread (2^R)
-    int32_t L;              // lut half width (-1: no lut)
+    int32_t L;              // lut half width (-1: no lut); entry m holds exp(-i gamma (m - L) qinv)
+    double qinv;            // 1/q: energies on the grid Z / q
     uint32_t qph_off;       // double2 offset of qph in the table buffer
     uint32_t lut_off;       // double2 offset of lut[0] (the entry for m = -L)
 };
@@ -137,7 +138,8 @@ struct PassArgs {
     int32_t grid;           // workgroups launched (< ntiles: persistent grid-stride walk), 0: one per tile
     int32_t stagger;        // persistent grids: start delay of the second half, in units of s_sleep(127)
     int32_t nphase;
-    int32_t lut_half;       // L of the integer phase tables, -1 for real-valued instances
+    int32_t lut_half;       // L of the phase tables (in units of 1/q), -1 for other real-valued instances
+    double lut_q;           // q: table index = q * energy
     uint32_t qph_off[kMaxPhase];
     uint32_t lut_off[kMaxPhase];
     double emin, etol;      // ground-state test |E - emin| <= etol

@@ -293,8 +293,9 @@ __device__ __forceinline__ void mix_round(Real (&vr)[NV][1 << R], Real (&vi)[NV]
     }
 }
 
-// Phase tables of one call: qph[r] = exp(-i gamma Q[r]) and, for integer-valued
-// instances, lut[m + L] = exp(-i gamma m), m = -L..L.  One workgroup per job.
+// Phase tables of one call: qph[r] = exp(-i gamma Q[r]) and, for instances whose
+// energies lie on the grid Z / q (integer or half-integer coefficients),
+// lut[m + L] = exp(-i gamma m / q), m = -L..L.  One workgroup per job.
 struct TableJobs {
     TableJob j[64];
 };
@@ -309,7 +310,7 @@ __global__ void __launch_bounds__(256) k_tables(const TableJobs jobs, double2* _
     if (jb.L >= 0) {
         for (int m = threadIdx.x; m <= 2 * jb.L; m += 256) {
             double sn, cs;
-            sincos(jb.gamma * (double)(m - jb.L), &sn, &cs);
+            sincos(jb.gamma * ((double)(m - jb.L) * jb.qinv), &sn, &cs);
             out[jb.lut_off + m] = make_double2(cs, -sn);
         }
     }
@@ -565,15 +566,15 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                     double2 gk[R];
                     double2 run;
                     if constexpr (INTE) {
-                        // integer energies: factors from the table exp(-i gamma m)
+                        // energies on the grid Z / q: factors from the table exp(-i gamma m / q)
                         const double2* __restrict__ lut = a.ptab + a.lut_off[op.qidx] + a.lut_half;
                         const int Lh = a.lut_half;
 #pragma unroll
                         for (int k = 0; k < R; k++) {
-                            const int m = min(max((int)(2.0 * f[k]), -Lh), Lh);
+                            const int m = min(max((int)(2.0 * f[k] * a.lut_q), -Lh), Lh);
                             gk[k] = lut[m];
                         }
-                        run = lut[min(max((int)e0, -Lh), Lh)];
+                        run = lut[min(max((int)(e0 * a.lut_q), -Lh), Lh)];
                     } else {
                         // One sincos at a time: the fma(0, previous sine, x) link (exact
                         // for finite values) keeps the scheduler from interleaving the

@@ -122,6 +122,24 @@ def fields_only(n: int, seed: int) -> dict:
     return make_instance(n, np.zeros((0, 2), dtype=np.int64), h, np.zeros(0))
 
 
+def exact_cover_matrix(nrows: int, ncols: int, seed: int, nplanted: int | None = None) -> np.ndarray:
+    """Boolean problem matrix a in {0,1}^{nrows x ncols} of an exact cover
+    instance (Sec. III.A.3 shape: N rows = qubits, F columns) with a planted
+    solution: `nplanted` rows (default nrows // 4) partition the columns (each
+    column in exactly one of them), every other row covers a uniformly random
+    column subset of the same expected size.  Only random draws; the Ising
+    form of the instance is computed by the library and by the oracle."""
+    rng = _rng(seed)
+    k = nplanted if nplanted is not None else max(1, nrows // 4)
+    a = np.zeros((nrows, ncols), dtype=np.uint8)
+    rows = rng.permutation(nrows)
+    planted = rows[:k]
+    a[planted[rng.integers(0, k, size=ncols)], np.arange(ncols)] = 1
+    for r in rows[k:]:
+        a[r] = (rng.random(ncols) < 1.0 / k).astype(np.uint8)
+    return a
+
+
 # --- the five workloads ----------------------------------------------------------
 
 def config0_instance() -> dict:

@@ -46,6 +46,8 @@ def _load():
         "sv_copy_from_host": (ip, [vp, vp, ctypes.c_size_t]),
         "sv_ising_create": (ip, [ip, dp, ip, i32p, i32p, dp, ctypes.POINTER(vp)]),
         "sv_ising_free": (ip, [vp]),
+        "sv_ising_exact_cover": (ip, [ip, ip, ctypes.POINTER(ctypes.c_uint8), dp, ctypes.POINTER(vp)]),
+        "sv_rescale_factor": (ip, [vp, dp]),
         "sv_ground": (ip, [vp, dp, u64p, u64p]),
         "sv_cost_phase": (ip, [vp, vp, ctypes.c_double]),
         "sv_mixer": (ip, [vp, ctypes.c_double]),
@@ -125,6 +127,22 @@ class Ising:
     def from_instance(cls, inst: dict) -> "Ising":
         return cls(inst["n"], inst["h"], inst["ei"], inst["ej"], inst["J"])
 
+    @classmethod
+    def exact_cover(cls, a):
+        """Ising form of the exact cover matrix a (rows = qubits, Sec. III.A.3)
+        built by the library: (instance, constant C), E(z) + C = objective."""
+        a = np.ascontiguousarray(np.asarray(a, dtype=np.uint8))
+        if a.ndim != 2:
+            raise ValueError("exact cover matrix must be 2-D")
+        obj = cls.__new__(cls)
+        handle = ctypes.c_void_p()
+        c = ctypes.c_double()
+        _check(lib.sv_ising_exact_cover(a.shape[0], a.shape[1], a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                        ctypes.byref(c), ctypes.byref(handle)))
+        obj._h = handle
+        obj.n, obj.m = a.shape[0], -1
+        return obj, c.value
+
     @property
     def handle(self):
         return self._h
@@ -139,6 +157,13 @@ class Ising:
             self.close()
         except Exception:
             pass
+
+
+def rescale_factor(H: Ising) -> float:
+    """r of Eq. rescale (apply as gamma / r and <H_C> * r)."""
+    r = ctypes.c_double()
+    _check(lib.sv_rescale_factor(H.handle, ctypes.byref(r)))
+    return r.value
 
 
 def ground(H: Ising):

@@ -102,6 +102,20 @@ def test_ising_validation(sv, case, code):
     assert sv.last_error() != ""
 
 
+def test_exact_cover_validation(sv):
+    out = ctypes.c_void_p()
+    c = ctypes.c_double()
+    bad = np.array([[0, 1, 2], [1, 0, 0]], dtype=np.uint8)
+    rc = sv.lib.sv_ising_exact_cover(2, 3, bad.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), ctypes.byref(c),
+                                     ctypes.byref(out))
+    assert rc == 1 and "not 0/1" in sv.last_error()
+    ok = np.zeros((2, 3), dtype=np.uint8)
+    assert sv.lib.sv_ising_exact_cover(0, 3, ok.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), None,
+                                       ctypes.byref(out)) == 1
+    assert sv.lib.sv_ising_exact_cover(2, 0, ok.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), None,
+                                       ctypes.byref(out)) == 1
+
+
 def test_state_validation(sv):
     out = ctypes.c_void_p()
     assert sv.lib.sv_wrap(10, 2, ctypes.c_void_p(0), 1 << 20, None, ctypes.byref(out)) == 1

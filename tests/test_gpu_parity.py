@@ -376,6 +376,39 @@ def test_one_instance_both_dtypes(sv, orc, first):
         assert np.max(np.abs(db - rb)) <= GRAD_TOL[dtype] * scale
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [9, 14, 17])
+def test_exact_cover_instances(sv, orc, dtype, n):
+    """Dense exact cover instances (half-integer h, J; Eqs. HChi-HCC): the
+    library's Ising form (ground energy -C, rescale factor), the QAOA state with
+    rescaled angles gamma / r, the fused observables and the adjoint gradient
+    against the oracle's independent construction."""
+    a = I.exact_cover_matrix(n, 472, 700 + n)
+    inst, C = orc.exact_cover_ising(a)
+    H, C_lib = sv.Ising.exact_cover(a)
+    assert C_lib == C
+    emin, deg, _ = sv.ground(H)
+    assert emin == -C and deg >= 1
+    r = sv.rescale_factor(H)
+    assert r == orc.rescale_factor(inst)
+    g, b = I.linear_ramp_params(3)
+    gr = g / r
+    E = orc.energies(inst)
+    ref = orc.qaoa_state(inst, gr, b, E=E)
+    s = sv.State(n, dtype)
+    e, pgs, nrm = sv.qaoa_energy(s, H, gr, b)
+    assert np.max(np.abs(s.to_numpy() - ref)) <= AMP_TOL[dtype]
+    _, ren, rpgs = orc.observables(inst, ref, E=E)
+    assert abs(e - ren) <= energy_tol(orc, inst, ren)
+    assert abs(pgs - rpgs) <= PROB_TOL[dtype]
+    lam = sv.State(n, dtype)
+    f, dg, db = sv.grad(s, lam, H, gr, b)
+    _, rg, rb = orc.grad_tangent(inst, gr, b, E=E)
+    scale = max(np.max(np.abs(np.concatenate([rg, rb]))), orc.coeff_scale(inst))
+    assert np.max(np.abs(dg - rg)) <= GRAD_TOL[dtype] * scale
+    assert np.max(np.abs(db - rb)) <= GRAD_TOL[dtype] * scale
+
+
 def test_grad_errors(sv):
     H = sv.Ising.from_instance(instance_for(10, "int", 1))
     a = sv.State(10, "c128")

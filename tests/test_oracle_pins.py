@@ -266,6 +266,29 @@ def test_product_state_factors_vs_full_state(orc, p):
         assert abs(orc.product_energy(inst["h"], g, b) - ref) < 1e-13
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_exact_cover_ising_matches_objective(orc, seed):
+    # Eqs. HChi-HCC: for every assignment, E(z) + C equals the exact cover
+    # objective computed directly from the Boolean matrix (brute force).
+    nr, nc = 9, 23
+    a = I.exact_cover_matrix(nr, nc, 100 + seed)
+    inst, C = orc.exact_cover_ising(a)
+    E = orc.energies(inst)
+    obj = np.array([orc.exact_cover_objective(a, z) for z in range(1 << nr)])
+    assert np.array_equal(E + C, obj.astype(np.float64))
+    # the planted rows form a cover: the minimum objective is 0, E_min = -C
+    assert obj.min() == 0 and E.min() == -C
+    # coefficients are half-integers (the grid the phase tables exploit)
+    assert np.all(2 * inst["h"] == np.round(2 * inst["h"])) and np.all(2 * inst["J"] == np.round(2 * inst["J"]))
+
+
+def test_rescale_factor_by_hand(orc):
+    inst = {"n": 3, "h": np.array([3.0, -5.0, 1.0]), "ei": np.array([0, 1], dtype=np.int32),
+            "ej": np.array([1, 2], dtype=np.int32), "J": np.array([1.5, -0.5])}
+    # max h / 2 = 1.5, min h / -2 = 2.5, max J / 1 = 1.5, min J / -1 = 0.5
+    assert orc.rescale_factor(inst) == 2.5
+
+
 def test_spin_z_against_dense(orc):
     inst = I.regular3_pm1(8, 3)
     psi = orc.qaoa_state(inst, [0.5, 1.0], [0.4, -0.2])
