@@ -162,11 +162,24 @@ int sv_qaoa_energy(sv_state s, sv_ising H, int p, const double* gamma, const dou
 int sv_aqa_run(sv_state s, sv_ising H, int steps, const double* gamma, const double* beta,
                double* pgs_per_step, double* energy_per_step);
 
+/* sv_aqa_run plus the spin expectations <sigma^z_i> after every step (the
+ * annealing observables of Sec. III.B.2): spinz_per_step receives steps * n
+ * values, row k = step k, column i = qubit i (sigma^z eigenvalue -1 for bit 0,
+ * Sec. III.A.3).  The n sums ride in the tile pass that ends each step.  Any
+ * output may be NULL; with a non-NULL output the call synchronises. */
+int sv_aqa_run_observe(sv_state s, sv_ising H, int steps, const double* gamma, const double* beta,
+                       double* pgs_per_step, double* energy_per_step, double* spinz_per_step);
+
 /* Observables of the current state (Sec. III.B.1): energy = <psi|H_C|psi>,
  * p_gs = sum of |psi(z)|^2 over the ground-state set of sv_ground (computed
  * first if needed), norm = <psi|psi>.  Any output pointer may be NULL.
  * FP64 accumulation, deterministic order.  Synchronises the stream. */
 int sv_expect(sv_state s, sv_ising H, double* energy, double* p_gs, double* norm);
+
+/* <psi|sigma^z_i|psi> for every qubit i of the current state (out: n values;
+ * sigma^z eigenvalue -1 for bit 0, Sec. III.A.3).  One read-only tile pass,
+ * FP64 sums in a fixed order.  Synchronises the stream. */
+int sv_spin_z(sv_state s, double* out);
 
 /* ---------------------------------------------------------------- adjoint --
  * Gradient of f(gamma, beta) = <beta,gamma| H_C |beta,gamma> with respect to

@@ -228,6 +228,8 @@ struct Work {
     double* d_res = nullptr;
     double* h_res = nullptr;
     size_t res_cap = 0;  // doubles
+    double* d_spin = nullptr;  // per-tile spin partials [ntiles][kTF]
+    size_t spin_cap = 0;       // doubles
 };
 
 struct sv_state_s {
@@ -653,7 +655,7 @@ static int get_geobuf(const Geometry& geo, sv_ising_s* H, sv_dtype dt, GeoBuf** 
 
 // ============================================================================ programs
 // Events of a circuit, in application order.
-enum EvKind { EV_INIT, EV_PHASE, EV_MIX, EV_REDUCE, EV_LAMINIT, EV_GGAMMA };
+enum EvKind { EV_INIT, EV_PHASE, EV_MIX, EV_REDUCE, EV_LAMINIT, EV_GGAMMA, EV_SPINZ };
 struct Event {
     EvKind kind;
     int group = 0;      // EV_MIX
@@ -671,6 +673,7 @@ struct Pass {
     std::vector<Op> ops;
     std::vector<int> slot_dst;                  // result index of each slot
     std::vector<std::pair<int, double>> phase;  // (layout, gamma) per phase table
+    int spin_res = -1;                          // PT_SPINZ: first result index of the n spin expectations
 };
 
 struct Program {
@@ -770,6 +773,7 @@ static Program build_program(const std::vector<Event>& evs, int nres, bool fuse)
         if (e.kind == EV_REDUCE) flag = PT_REDUCE;
         if (e.kind == EV_LAMINIT) flag = PT_LAM_INIT;
         if (e.kind == EV_GGAMMA) flag = PT_GGAMMA;
+        if (e.kind == EV_SPINZ) flag = PT_SPINZ;
         const int slots = e.kind == EV_REDUCE ? 3 : (e.kind == EV_GGAMMA ? 1 : 0);
         bool merge = false;
         if (open && has_point && nmix_post == 0) {
@@ -779,7 +783,9 @@ static Program build_program(const std::vector<Event>& evs, int nres, bool fuse)
                 // a reduction reads only |psi|^2 and E, which a phase leaves alone
                 const int mine = point_rank(flag);
                 const int lastmax = point_rank(last.flags);
-                merge = mine > lastmax || (flag == PT_REDUCE && !(last.flags & (PT_LAM_INIT | PT_GGAMMA)));
+                // (spin sums, like the reduction, read only |psi|^2)
+                merge = mine > lastmax ||
+                        ((flag == PT_REDUCE || flag == PT_SPINZ) && !(last.flags & (PT_LAM_INIT | PT_GGAMMA)));
             }
         }
         bool fits = open && (!fuse ? !cur.has_mix : true) && (int)cur.slot_dst.size() + slots <= limit(e);
@@ -814,6 +820,8 @@ static Program build_program(const std::vector<Event>& evs, int nres, bool fuse)
             cur.phase.push_back({-1, e.angle});
         } else if (e.kind == EV_LAMINIT) {
             lam_live = true;
+        } else if (e.kind == EV_SPINZ) {
+            cur.spin_res = e.res;
         }
     }
     close();
@@ -956,6 +964,16 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         part_need = std::max(part_need, (size_t)plan.by_nv[p.nv][p.group].ntiles * std::max<size_t>(1, p.slot_dst.size()));
     int rc = ensure_work(s, part_need, std::max(prog.nres, 1));
     if (rc) return rc;
+    size_t spin_need = 0;
+    for (const Pass& p : prog.passes)
+        if (p.spin_res >= 0) spin_need = std::max(spin_need, (size_t)plan.by_nv[p.nv][p.group].ntiles * kTF);
+    if (spin_need > s->w.spin_cap) {
+        if (s->w.d_spin) (void)hipFree(s->w.d_spin);
+        s->w.d_spin = nullptr;
+        s->w.spin_cap = 0;
+        HIPCHECK(hipMalloc(&s->w.d_spin, spin_need * sizeof(double)));
+        s->w.spin_cap = spin_need;
+    }
     if (prog.nres > 0) {
         hipError_t e = hipMemsetAsync(s->w.d_res, 0, prog.nres * sizeof(double), s->stream);
         if (e != hipSuccess) {
@@ -1051,6 +1069,7 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         a.ptab = s->w.d_tab;
         a.lut_half = lut_half;
         a.lut_q = H && H->qden > 0 ? (double)H->qden : 1.0;
+        a.spin_part = p.spin_res >= 0 ? s->w.d_spin : nullptr;
         for (int q = 0; q < a.nphase; q++) {
             a.qph_off[q] = offs[pi][q].first;
             a.lut_off[q] = offs[pi][q].second;
@@ -1072,6 +1091,24 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         if (e != 0) {
             s->failed = true;
             return fail(SV_ERR_HIP, "pass launch failed: %s", hipGetErrorString((hipError_t)e));
+        }
+        if (p.spin_res >= 0) {
+            SpinArgs sa;
+            memset(&sa, 0, sizeof(sa));
+            sa.part = s->w.d_spin;
+            sa.ntiles = geo.ntiles;
+            sa.c = geo.c;
+            sa.lo = geo.lo;
+            sa.g = geo.g;
+            sa.T = geo.T;
+            sa.n = s->n;
+            for (int l = 0; l < 16; l++) sa.qubit[l] = l < geo.T ? global_bit(geo, l) : -1;
+            sa.out = s->w.d_res + p.spin_res;
+            e = launch_spin_reduce(sa, s->stream);
+            if (e != 0) {
+                s->failed = true;
+                return fail(SV_ERR_HIP, "spin reduce launch failed: %s", hipGetErrorString((hipError_t)e));
+            }
         }
         if (a.nslots > 0) {
             e = launch_reduce_slots(s->w.d_part, geo.ntiles, a.nslots, p.slot_dst.data(), 1, s->w.d_res,
@@ -1148,6 +1185,7 @@ extern "C" int sv_free(sv_state s) {
     if (!s) return SV_OK;
     if (s->owned && s->ptr) (void)hipFree(s->ptr);
     if (s->w.d_part) (void)hipFree(s->w.d_part);
+    if (s->w.d_spin) (void)hipFree(s->w.d_spin);
     if (s->w.d_tab) (void)hipFree(s->w.d_tab);
     if (s->w.d_res) (void)hipFree(s->w.d_res);
     if (s->w.h_res) (void)hipHostFree(s->w.h_res);
@@ -1550,26 +1588,68 @@ extern "C" int sv_qaoa_energy(sv_state s, sv_ising H, int p, const double* gamma
     return SV_OK;
 }
 
-extern "C" int sv_aqa_run(sv_state s, sv_ising H, int steps, const double* gamma, const double* beta,
-                          double* pgs_per_step, double* energy_per_step) {
+extern "C" int sv_aqa_run_observe(sv_state s, sv_ising H, int steps, const double* gamma, const double* beta,
+                                  double* pgs_per_step, double* energy_per_step, double* spinz_per_step) {
     int rc = check_pair(s, H, "sv_aqa_run");
     if (rc) return rc;
     rc = check_angles(steps, gamma, beta, "sv_aqa_run");
     if (rc) return rc;
     const bool want = pgs_per_step || energy_per_step;
+    const bool spins = spinz_per_step != nullptr;
     Plan plan = make_plan(s->n, s->dt);
     std::vector<Event> ev;
     forward_events(ev, group_order((int)plan.by_nv[1].size(), (int)s->dt, s->n), steps, gamma, beta, true,
                    want ? 0 : -1);
-    Program prog = build_program(ev, want ? 3 * steps : 0, knob_for("fuse", (int)s->dt, s->n) != 0);
+    // per-step spin sums ride in the pass that ends each step (after its reduction, if any)
+    const int nres = (want ? 3 * steps : 0) + (spins ? steps * s->n : 0);
+    if (spins) {
+        std::vector<Event> with;
+        int k = 0;
+        for (size_t i = 0; i < ev.size(); i++) {
+            with.push_back(ev[i]);
+            const bool step_end = (i + 1 == ev.size()) || ev[i + 1].kind == EV_PHASE;
+            if (step_end && ev[i].kind != EV_INIT && ev[i].kind != EV_PHASE) {
+                Event sz{EV_SPINZ};
+                sz.res = (want ? 3 * steps : 0) + k * s->n;
+                with.push_back(sz);
+                k++;
+            }
+        }
+        ev.swap(with);
+    }
+    Program prog = build_program(ev, nres, knob_for("fuse", (int)s->dt, s->n) != 0);
     rc = run_program(s, nullptr, H, prog, plan, want);
-    if (rc || !want) return rc;
-    rc = fetch_results(s, 3 * steps);
+    if (rc || nres == 0) return rc;
+    rc = fetch_results(s, nres);
     if (rc) return rc;
     for (int k = 0; k < steps; k++) {
         if (pgs_per_step) pgs_per_step[k] = s->w.h_res[3 * k + 2];
         if (energy_per_step) energy_per_step[k] = s->w.h_res[3 * k + 1];
     }
+    if (spins) {
+        const double* sp = s->w.h_res + (want ? 3 * steps : 0);
+        for (int k = 0; k < steps * s->n; k++) spinz_per_step[k] = sp[k];
+    }
+    return SV_OK;
+}
+
+extern "C" int sv_aqa_run(sv_state s, sv_ising H, int steps, const double* gamma, const double* beta,
+                          double* pgs_per_step, double* energy_per_step) {
+    return sv_aqa_run_observe(s, H, steps, gamma, beta, pgs_per_step, energy_per_step, nullptr);
+}
+
+extern "C" int sv_spin_z(sv_state s, double* out) {
+    if (!s || !out) return fail(SV_ERR_ARG, "sv_spin_z: NULL argument");
+    Plan plan = make_plan(s->n, s->dt);
+    Event sz{EV_SPINZ};
+    sz.res = 0;
+    Program prog = build_program({sz}, s->n, true);
+    prog.passes[0].store = 0;
+    int rc = run_program(s, nullptr, nullptr, prog, plan, false);
+    if (rc) return rc;
+    rc = fetch_results(s, s->n);
+    if (rc) return rc;
+    for (int i = 0; i < s->n; i++) out[i] = s->w.h_res[i];
     return SV_OK;
 }
 

@@ -47,7 +47,18 @@ enum PointFlags : int32_t {
     PT_LAM_INIT = 2,   // lam = E psi
     PT_GGAMMA = 4,     // slot2 += E Im(conj(lam) psi)
     PT_PHASE_PSI = 8,  // psi *= exp(-i gamma E)
-    PT_PHASE_LAM = 16  // lam *= exp(-i gamma E); two-vector passes phase both or neither
+    PT_PHASE_LAM = 16,  // lam *= exp(-i gamma E); two-vector passes phase both or neither
+    PT_SPINZ = 32       // spin sums: per tile, sum |psi|^2 s_l for every tile bit l and sum |psi|^2
+};
+
+// Per-tile spin partials (PT_SPINZ): kTF doubles per tile, entry l < T =
+// sum over the tile of |psi|^2 s_l, entry kTF - 1 = sum of |psi|^2.
+struct SpinArgs {
+    const double* part;     // [ntiles][kTF]
+    uint64_t ntiles;
+    int32_t c, lo, g, T, n;
+    int32_t qubit[16];      // tile bit -> qubit (-1: phantom)
+    double* out;            // [n]: <sigma^z_i>
 };
 
 struct Op {
@@ -140,6 +151,7 @@ struct PassArgs {
     int32_t nphase;
     int32_t lut_half;       // L of the phase tables (in units of 1/q), -1 for other real-valued instances
     double lut_q;           // q: table index = q * energy
+    double* spin_part;      // [ntiles][kTF] spin partials (passes with PT_SPINZ)
     uint32_t qph_off[kMaxPhase];
     uint32_t lut_off[kMaxPhase];
     double emin, etol;      // ground-state test |E - emin| <= etol
@@ -173,6 +185,7 @@ struct TfArgs {
 int launch_pass(int dtype, int nv, int T, const PassArgs& a, void* stream);
 int launch_tile_fields(const TfArgs& a, void* stream);
 int launch_tables(const TableJob* jobs, int njobs, double2* out, void* stream);
+int launch_spin_reduce(const SpinArgs& a, void* stream);
 int launch_reduce_slots(const double* partials, uint64_t nrows, int nslots, const int* dst,
                         int accumulate, double* out, void* stream);
 int launch_ground(int dtype, const GroundArgs& a, void* stream);

@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(256) k_tables(const TableJobs jobs, double2* _
 // layout walks); KC == 0: generic kernel with a runtime layout count (used for
 // states smaller than one tile and for real-valued instances).
 template <typename Real, int T, int R, int NV, int NS, int MINB, bool PH, bool INTE, int KC, int NTM = 0,
-          bool PERSIST = false>
+          bool PERSIST = false, bool SPZ = PH>
 __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
     using V2 = typename V2T<Real>::type;
     constexpr int NT = 1 << (T - R);
@@ -335,6 +335,7 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
     __shared__ V2 xbuf[FULLX ? (1 << T) : (1 << (T - 1))];
     __shared__ double s_g[kTF];  // tile fields g_l and E_fixed (entry kTF - 1)
     __shared__ double s_red[NW][NS];
+    __shared__ double s_spin[NW][kTF];  // per-wave spin sums (PT_SPINZ)
 
     const uint32_t t = threadIdx.x;
     const GeoBuf* __restrict__ geo = a.geo;
@@ -420,6 +421,8 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
         if ((t & 63) == 0) {
 #pragma unroll
             for (int q = 0; q < NS; q++) s_red[t >> 6][q] = 0.0;
+#pragma unroll
+            for (int q = 0; q < kTF; q++) s_spin[t >> 6][q] = 0.0;
         }
         double pend[NV];  // uniform scale every register of vector v still has to be multiplied by
 #pragma unroll
@@ -520,8 +523,16 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                 const double e0 = thread_energy<R, T - R>(L, geo, t, s_g, f);
                 const int fl = op.flags;
                 // E of register r = e0 + (Gray-walk sum of +-2 f[k]) + Q[r]
-                if (fl & (PT_REDUCE | PT_LAM_INIT | PT_GGAMMA)) {
+                if (fl & (PT_REDUCE | PT_LAM_INIT | PT_GGAMMA | PT_SPINZ)) {
+                    // one sweep over the registers feeds every reduction of the op
+                    // (|psi|^2 is formed once; the spin sums of one-vector passes
+                    // take it for each register bit k: +-|psi|^2 by bit k of r)
                     double r_n = 0.0, r_e = 0.0, r_p = 0.0, r_g = 0.0;
+                    double Sk[R];
+#pragma unroll
+                    for (int k = 0; k < R; k++) Sk[k] = 0.0;
+                    // spin sums exist in the generic kernels and in dedicated fast variants
+                    const bool spins = SPZ && NV == 1 && (fl & PT_SPINZ) != 0;
                     double e_run = e0;
 #pragma unroll
                     for (int i = 0; i < NR; i++) {
@@ -532,11 +543,15 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                         }
                         const double e = e_run + L->Q[r];
                         const double pr = (double)vr[0][r], pi = (double)vi[0][r];
-                        if (fl & PT_REDUCE) {
+                        if (fl & (PT_REDUCE | PT_SPINZ)) {
                             const double p2 = pr * pr + pi * pi;
                             r_n += p2;
                             r_e += e * p2;
                             if (fabs(e - a.emin) <= a.etol) r_p += p2;
+                            if (spins) {
+#pragma unroll
+                                for (int k = 0; k < R; k++) Sk[k] += ((r >> k) & 1) ? p2 : -p2;
+                            }
                         }
                         if constexpr (NV == 2) {
                             if (fl & PT_LAM_INIT) {
@@ -549,11 +564,27 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                             }
                         }
                     }
+                    const double s2 = pend[0] * pend[0];
                     if (fl & PT_REDUCE) {
-                        const double s2 = pend[0] * pend[0];
                         wave_add<NS>(s_red, op.slot, r_n * s2);
                         wave_add<NS>(s_red, op.slot + 1, r_e * s2);
                         wave_add<NS>(s_red, op.slot + 2, r_p * s2);
+                    }
+                    if constexpr (NV == 1 && SPZ) {
+                        if (spins) {
+                            // tile bit l: register bit k -> Sk[k]; thread bit j -> +-norm
+                            const uint32_t rbp = L->rbpack;
+#pragma unroll
+                            for (int k = 0; k < R; k++) wave_add<kTF>(s_spin, (rbp >> (4 * k)) & 15u, Sk[k] * s2);
+                            uint32_t m = L->tmask;
+#pragma unroll
+                            for (int j = 0; j < T - R; j++) {
+                                const int l = __builtin_ctz(m);
+                                m &= m - 1u;
+                                wave_add<kTF>(s_spin, l, ((t >> j) & 1u) ? r_n * s2 : -r_n * s2);
+                            }
+                            wave_add<kTF>(s_spin, kTF - 1, r_n * s2);
+                        }
                     }
                     if constexpr (NV == 2) {
                         if (fl & PT_LAM_INIT) pend[1] = pend[0];
@@ -654,12 +685,17 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
         }
 
         // ---- per-tile partial sums, fixed order
-        if (a.nslots > 0) {
+        if (a.nslots > 0 || (SPZ && a.spin_part)) {
             __syncthreads();
             if ((int)t < a.nslots) {
                 double v = 0.0;
                 for (int ww = 0; ww < NW; ww++) v += s_red[ww][t];
                 a.partials[tile * (uint64_t)a.nslots + t] = v;
+            }
+            if (SPZ && a.spin_part && t < kTF) {
+                double v = 0.0;
+                for (int ww = 0; ww < NW; ww++) v += s_spin[ww][t];
+                a.spin_part[tile * kTF + t] = v;
             }
         }
         if constexpr (!PERSIST) break;
@@ -691,6 +727,36 @@ __global__ void __launch_bounds__(256) k_reduce_slots(const double* __restrict__
         const int d = dst.d[s];
         out[d] = accumulate ? out[d] + sh[0] : sh[0];
     }
+}
+
+// <sigma^z_i> from the per-tile spin partials, one workgroup per qubit in a fixed
+// order: a qubit held by tile bit l sums entry l over the tiles; any other qubit
+// is fixed within a tile, so it sums s_i(tile) times the tile's norm entry.
+__global__ void __launch_bounds__(256) k_spin_reduce(const SpinArgs a) {
+    __shared__ double sh[256];
+    const int i = blockIdx.x;
+    const int t = threadIdx.x;
+    int l = -1;
+    for (int q = 0; q < a.T; q++)
+        if (a.qubit[q] == i) l = q;
+    const TileGeom tg{a.c, a.lo, a.g};
+    double v = 0.0;
+    for (uint64_t w = t; w < a.ntiles; w += 256) {
+        const double* row = a.part + w * kTF;
+        v += l >= 0 ? row[l] : spin_z(tg.base(w), i) * row[kTF - 1];
+    }
+    sh[t] = v;
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+        if (t < s) sh[t] += sh[t + s];
+        __syncthreads();
+    }
+    if (t == 0) a.out[i] = sh[0];
+}
+
+int launch_spin_reduce(const SpinArgs& a, void* stream) {
+    hipLaunchKernelGGL(k_spin_reduce, dim3((unsigned)a.n), dim3(256), 0, (hipStream_t)stream, a);
+    return (int)hipGetLastError();
 }
 
 // Brute-force enumeration of E(z) over all basis states, tile by tile in layout 0.
@@ -841,6 +907,18 @@ static int run_pass(const PassArgs& a, void* stream) {
         // the register pressure below the two-workgroups-per-CU limit
         // (nontemporal variants for passes over long contiguous runs)
         if constexpr (NV == 1) {
+            if (a.spin_part) {  // passes that also sum the spin expectations
+                if (a.nlayouts == 1)
+                    hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 1, 0, false, true>), grid, block,
+                                       0, st, a);
+                else if (a.nlayouts == 2)
+                    hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 2, 0, false, true>), grid, block,
+                                       0, st, a);
+                else
+                    hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 0, 0, false, true>), grid, block,
+                                       0, st, a);
+                return (int)hipGetLastError();
+            }
             if (pers) {
                 if (a.nlayouts == 2)
                     hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 2, 0, true>), grid, block, 0, st,

@@ -54,6 +54,8 @@ def _load():
         "sv_qaoa_forward": (ip, [vp, vp, ip, dp, dp, ip]),
         "sv_qaoa_energy": (ip, [vp, vp, ip, dp, dp, ip, dp, dp, dp]),
         "sv_aqa_run": (ip, [vp, vp, ip, dp, dp, dp, dp]),
+        "sv_aqa_run_observe": (ip, [vp, vp, ip, dp, dp, dp, dp, dp]),
+        "sv_spin_z": (ip, [vp, dp]),
         "sv_expect": (ip, [vp, vp, dp, dp, dp]),
         "sv_grad": (ip, [vp, vp, vp, ip, dp, dp, ip, dp, dp, dp]),
         "sv_schedule_linear": (ip, [ip, ctypes.c_double, ip, dp, dp]),
@@ -281,6 +283,25 @@ def aqa_run(s: State, H: Ising, gamma, beta, per_step: bool = False):
     null = ctypes.POINTER(ctypes.c_double)()
     _check(lib.sv_aqa_run(s.handle, H.handle, len(g), _dp(g), _dp(b), null, null))
     return None
+
+
+def aqa_run_observe(s: State, H: Ising, gamma, beta):
+    """AQA run returning per-step (P_gs[steps], <H_C>[steps], <sigma^z>[steps, n])."""
+    g, b = _f64(gamma), _f64(beta)
+    if len(g) != len(b):
+        raise ValueError("gamma and beta must have equal length")
+    pg = np.empty(len(g))
+    en = np.empty(len(g))
+    sz = np.empty((len(g), s.n))
+    _check(lib.sv_aqa_run_observe(s.handle, H.handle, len(g), _dp(g), _dp(b), _dp(pg), _dp(en), _dp(sz)))
+    return pg, en, sz
+
+
+def spin_z(s: State) -> np.ndarray:
+    """<sigma^z_i> of the current state for every qubit i."""
+    out = np.empty(s.n)
+    _check(lib.sv_spin_z(s.handle, _dp(out)))
+    return out
 
 
 def expect(s: State, H: Ising):

@@ -307,6 +307,44 @@ def test_aqa_per_step(sv, orc, dtype, n):
     assert np.max(np.abs(s.to_numpy() - psi)) <= AMP_TOL[dtype]
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [3, 12, 14, 17, 23])
+def test_spin_z(sv, orc, dtype, n):
+    inst = instance_for(n, "int" if n % 2 else "real", 180 + n)
+    H = sv.Ising.from_instance(inst)
+    g, b = I.uniform_params(2, 181 + n, -1.0, 1.0)
+    s = sv.State(n, dtype)
+    sv.qaoa_forward(s, H, g, b)
+    got = sv.spin_z(s)
+    ref = orc.spin_z(n, orc.qaoa_state(inst, g, b))
+    assert np.max(np.abs(got - ref)) <= PROB_TOL[dtype] * 10
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [8, 14, 19])
+def test_aqa_per_step_spins(sv, orc, dtype, n):
+    """Per-step <sigma^z_i>, P_gs and <H_C> of an AQA run (fused into the step
+    passes) against the oracle, step by step."""
+    inst = instance_for(n, "int", 190 + n)
+    H = sv.Ising.from_instance(inst)
+    steps = 6
+    g, b = sv.schedule_linear(steps, 0.8)
+    s = sv.State(n, dtype)
+    pg, en, sz = sv.aqa_run_observe(s, H, g, b)
+    E = orc.energies(inst)
+    gs = orc.ground(inst, E)
+    psi = orc.plus_state(n)
+    for k in range(steps):
+        psi = orc.qaoa_state(inst, [g[k]], [b[k]], psi0=psi, E=E)
+        _, ren, rpg = orc.observables(inst, psi, E=E, gs=gs)
+        assert abs(en[k] - ren) <= energy_tol(orc, inst, ren)
+        assert abs(pg[k] - rpg) <= PROB_TOL[dtype]
+        assert np.max(np.abs(sz[k] - orc.spin_z(n, psi))) <= PROB_TOL[dtype] * 10
+    # same state as the plain AQA call
+    pg2, en2 = sv.aqa_run(s, H, g, b, per_step=True)
+    assert np.max(np.abs(en2 - en)) <= 1e-12 * max(1.0, np.max(np.abs(en)))
+
+
 def test_aqa_equals_qaoa_call(sv, orc):
     """AQA with n steps is one QAOA call with p = n + 1 (Sec. III.B.2)."""
     n = 16
