@@ -163,6 +163,28 @@ def main():
                                  "couplings": int(np.count_nonzero(np.triu(a.astype(np.int64) @ a.T.astype(np.int64), 1))),
                                  "rescale_r": rx, "energy_plus_C": ox[0] * 1.0 + Cx, "p_gs": ox[1]}
         log(f"[bench] exact cover {msx:.3f} ms/step")
+        del Hx
+        # optimisation loop of the paper (SLSQP, 200-call cap) at n = 26, p = 4:
+        # adjoint gradients against scipy's finite differences of energy calls
+        from paper_2104_03293_amd import optimize as O
+        Ho = sv.Ising.from_instance(I.config1_instance(26))
+        dev = O.DeviceQAOA(Ho, args.dtype)
+        g0, b0 = O.second_order_init(p, 0.5)
+        opt = {}
+        for label, ug in (("adjoint", True), ("finite_diff", False)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = O.optimize_qaoa(dev, g0, b0, method="SLSQP", max_calls=200, use_grad=ug)
+            torch.cuda.synchronize()
+            opt[label] = {"seconds": round(time.perf_counter() - t0, 3), "calls": r.calls, "grad_calls": r.grad_calls,
+                          "energy": r.energy, "p_gs": r.p_gs, "converged": r.converged,
+                          "fd_equivalent_calls": r.fd_equivalent_calls}
+        e_init, _ = dev.energy(g0, b0)
+        extras["optimizer"] = {"instance": "G(26,52), J in [-2,2], h in {-1,0,1}, seed 1", "p": p, "method": "SLSQP",
+                               "initial_energy": e_init, **opt}
+        log(f"[bench] optimizer adjoint {opt['adjoint']['seconds']} s, FD {opt['finite_diff']['seconds']} s")
+        dev.close()
+        del Ho
 
     cpu = None
     if not args.no_extras:

@@ -189,11 +189,12 @@ int sv_spin_z(sv_state s, double* out);
  *   psi, lam: two states with equal n and dtype (lam is scratch).
  *   psi_is_forward != 0: psi already holds the QAOA state for (gamma, beta);
  *   otherwise the forward circuit is run from |+>^n first.
- *   Outputs: energy (may be NULL), dgamma[p], dbeta[p] (host).
+ *   Outputs: energy and p_gs (the ground-state probability of the same state,
+ *   Sec. III.B.1; either may be NULL), dgamma[p], dbeta[p] (host).
  * On return psi and lam hold unspecified values.  Synchronises. */
 int sv_grad(sv_state psi, sv_state lam, sv_ising H, int p, const double* gamma,
-            const double* beta, int psi_is_forward, double* energy, double* dgamma,
-            double* dbeta);
+            const double* beta, int psi_is_forward, double* energy, double* p_gs,
+            double* dgamma, double* dbeta);
 
 /* ------------------------------------------------------------- schedules --
  * Host-only helpers that fill gamma[], beta[] (no GPU work).

@@ -1675,7 +1675,7 @@ extern "C" int sv_expect(sv_state s, sv_ising H, double* energy, double* p_gs, d
 // pgs; [3 + k] = sum E Im(conj lam psi) for gamma_k; [3 + p + k] = pair sums
 // for beta_k.  df/dgamma_k = 2 * res[3+k], df/dbeta_k = 2 * res[3+p+k].
 extern "C" int sv_grad(sv_state psi, sv_state lam, sv_ising H, int p, const double* gamma, const double* beta,
-                       int psi_is_forward, double* energy, double* dgamma, double* dbeta) {
+                       int psi_is_forward, double* energy, double* p_gs, double* dgamma, double* dbeta) {
     int rc = check_pair(psi, H, "sv_grad");
     if (rc) return rc;
     if (!lam) return fail(SV_ERR_ARG, "sv_grad: NULL lam state");
@@ -1733,11 +1733,12 @@ extern "C" int sv_grad(sv_state psi, sv_state lam, sv_ising H, int p, const doub
         }
     }
     prog.passes.back().store = 0;
-    rc = run_program(psi, lam, H, prog, plan, false);
+    rc = run_program(psi, lam, H, prog, plan, p_gs != nullptr);
     if (rc) return rc;
     rc = fetch_results(psi, 3 + 2 * p);
     if (rc) return rc;
     if (energy) *energy = psi->w.h_res[1];
+    if (p_gs) *p_gs = psi->w.h_res[2];
     for (int k = 0; k < p; k++) {
         dgamma[k] = 2.0 * psi->w.h_res[3 + k];
         dbeta[k] = 2.0 * psi->w.h_res[3 + p + k];

@@ -31,6 +31,11 @@ def _load():
         raise ImportError(
             f"{LIB_PATH} is missing: build it with `python -m paper_2104_03293_amd.build` "
             "(the HIP library is required; there is no fallback)")
+    # torch ships its own HIP runtime under the same soname; loading torch first
+    # makes libsv.so bind to that copy, so the process holds one runtime and
+    # torch's streams and allocations are valid handles for the library
+    import torch  # noqa: F401
+
     L = ctypes.CDLL(str(LIB_PATH))
     vp, dp, ip, u64p, i32p = (ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int,
                               ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int32))
@@ -57,7 +62,7 @@ def _load():
         "sv_aqa_run_observe": (ip, [vp, vp, ip, dp, dp, dp, dp, dp]),
         "sv_spin_z": (ip, [vp, dp]),
         "sv_expect": (ip, [vp, vp, dp, dp, dp]),
-        "sv_grad": (ip, [vp, vp, vp, ip, dp, dp, ip, dp, dp, dp]),
+        "sv_grad": (ip, [vp, vp, vp, ip, dp, dp, ip, dp, dp, dp, dp]),
         "sv_schedule_linear": (ip, [ip, ctypes.c_double, ip, dp, dp]),
         "sv_schedule_second_order": (ip, [ip, ctypes.c_double, dp, dp, dp, dp]),
         "sv_batch_p1_scan": (ip, [ip, ctypes.POINTER(vp), ip, dp, ip, dp, ip, vp, dp, dp]),
@@ -311,16 +316,19 @@ def expect(s: State, H: Ising):
     return e.value, p.value, n.value
 
 
-def grad(psi: State, lam: State, H: Ising, gamma, beta, psi_is_forward: bool = False):
-    """(energy, dE/dgamma[p], dE/dbeta[p]) by the adjoint reverse sweep."""
+def grad(psi: State, lam: State, H: Ising, gamma, beta, psi_is_forward: bool = False, with_pgs: bool = False):
+    """(energy, dE/dgamma[p], dE/dbeta[p]) by the adjoint reverse sweep;
+    with_pgs=True: (energy, p_gs, dE/dgamma[p], dE/dbeta[p])."""
     g, b = _f64(gamma), _f64(beta)
     if len(g) != len(b):
         raise ValueError("gamma and beta must have equal length")
-    e = ctypes.c_double()
+    e, pg = ctypes.c_double(), ctypes.c_double()
     dg = np.empty(len(g))
     db = np.empty(len(g))
     _check(lib.sv_grad(psi.handle, lam.handle, H.handle, len(g), _dp(g), _dp(b), int(bool(psi_is_forward)),
-                       ctypes.byref(e), _dp(dg), _dp(db)))
+                       ctypes.byref(e), ctypes.byref(pg), _dp(dg), _dp(db)))
+    if with_pgs:
+        return e.value, pg.value, dg, db
     return e.value, dg, db
 
 

@@ -368,10 +368,12 @@ def test_grad_vs_oracle(sv, orc, dtype, n, p):
     g, b = I.uniform_params(p, 130 + n + p, -1.0, 1.0)
     psi = sv.State(n, dtype)
     lam = sv.State(n, dtype)
-    e, dg, db = sv.grad(psi, lam, H, g, b)
+    e, pg, dg, db = sv.grad(psi, lam, H, g, b, with_pgs=True)
     f, rg, rb = orc.grad_tangent(inst, g, b)
+    _, _, rpg = orc.observables(inst, orc.qaoa_state(inst, g, b))
     scale = max(np.max(np.abs(np.concatenate([rg, rb]))), orc.coeff_scale(inst))
     assert abs(e - f) <= energy_tol(orc, inst, f)
+    assert abs(pg - rpg) <= PROB_TOL[dtype]
     assert np.max(np.abs(dg - rg)) <= GRAD_TOL[dtype] * scale
     assert np.max(np.abs(db - rb)) <= GRAD_TOL[dtype] * scale
 

@@ -1,0 +1,171 @@
+"""The QAOA optimisation loop (Sec. III.B.1, Sec. IV.A): budget, accounting,
+rescaling (Eq. rescale) and agreement of the GPU-driven loop with an
+oracle-driven one."""
+import json
+
+import numpy as np
+import pytest
+
+from paper_2104_03293_amd import inputs as I
+from paper_2104_03293_amd import optimize as O
+
+
+class OracleQAOA:
+    """Simulator interface of the optimisation loop, backed by the FP64 oracle."""
+
+    def __init__(self, orc, inst):
+        self.orc, self.inst = orc, inst
+        self.E = orc.energies(inst)
+        self.gs = orc.ground(inst, self.E)
+
+    def energy(self, gamma, beta):
+        psi = self.orc.qaoa_state(self.inst, gamma, beta, E=self.E)
+        _, e, pg = self.orc.observables(self.inst, psi, E=self.E, gs=self.gs)
+        return e, pg
+
+    def energy_grad(self, gamma, beta):
+        f, dg, db = self.orc.grad_tangent(self.inst, gamma, beta, E=self.E)
+        _, pg = self.energy(gamma, beta)
+        return f, pg, dg, db
+
+
+def small_problem(orc, n=6, seed=11):
+    inst = I.degree4_int2(n, seed)
+    return inst, OracleQAOA(orc, inst)
+
+
+@pytest.mark.parametrize("method", O.PAPER_METHODS)
+def test_budget_is_a_hard_cap(orc, method):
+    _, sim = small_problem(orc)
+    g0, b0 = I.linear_ramp_params(2)
+    res = O.optimize_qaoa(sim, g0, b0, method=method, max_calls=5, tol=1e-14)
+    assert res.calls == len(res.history) <= 5
+    assert res.budget_hit and not res.converged
+    assert res.energy == min(c.energy for c in res.history)
+    assert res.fd_equivalent_calls == res.energy_calls + res.grad_calls * (2 * res.p + 1)
+    if method == "Nelder-Mead":
+        assert res.grad_calls == 0
+    else:
+        assert res.energy_calls == 0
+
+
+@pytest.mark.parametrize("method", O.PAPER_METHODS)
+def test_optimizers_lower_the_energy(orc, method):
+    inst, sim = small_problem(orc)
+    g0, b0 = I.linear_ramp_params(2)
+    e0, _ = sim.energy(g0, b0)
+    res = O.optimize_qaoa(sim, g0, b0, method=method, max_calls=200)
+    assert res.energy < e0 - 1e-3
+    # the reported point reproduces the reported energy
+    e1, p1 = sim.energy(res.gamma, res.beta)
+    assert abs(e1 - res.energy) <= 1e-12 * max(1.0, orc.coeff_scale(inst))
+    assert abs(p1 - res.p_gs) <= 1e-12
+
+
+def test_gradient_method_converges_to_a_stationary_point(orc):
+    inst, sim = small_problem(orc)
+    g0, b0 = I.linear_ramp_params(2)
+    res = O.optimize_qaoa(sim, g0, b0, method="L-BFGS-B", max_calls=200, options={"gtol": 1e-9})
+    assert res.converged
+    _, _, dg, db = sim.energy_grad(res.gamma, res.beta)
+    assert np.max(np.abs(np.concatenate([dg, db]))) <= 1e-6 * orc.coeff_scale(inst)
+
+
+def test_rescaled_objective_and_chain_rule(orc):
+    """With scale r the optimiser works on H_C/r in the variables (r gamma, beta):
+    its gradient must match central differences of the objective it sees."""
+    inst, sim = small_problem(orc)
+    r = 3.25
+    seen = []
+
+    class Spy:
+        def energy(self, g, b):
+            return sim.energy(g, b)
+
+        def energy_grad(self, g, b):
+            out = sim.energy_grad(g, b)
+            seen.append((np.asarray(g), np.asarray(b), out))
+            return out
+
+    g0, b0 = I.uniform_params(2, 5, -0.5, 0.5)
+    O.optimize_qaoa(Spy(), g0, b0, method="L-BFGS-B", max_calls=1, scale=r)
+    g, b, (e, _, dg, db) = seen[0]
+    assert np.allclose(g, g0) and np.allclose(b, b0)   # original units reach the simulator
+    x = np.concatenate([g * r, b])
+
+    def obj(x):
+        return sim.energy(x[:2] / r, x[2:])[0] / r
+
+    h = 1e-5
+    num = np.array([(obj(x + h * np.eye(4)[k]) - obj(x - h * np.eye(4)[k])) / (2 * h) for k in range(4)])
+    ana = np.concatenate([dg / (r * r), db / r])
+    assert np.max(np.abs(num - ana)) <= 1e-7 * max(1.0, np.max(np.abs(ana)))
+
+
+def test_rescaling_reports_original_units(orc):
+    inst, sim = small_problem(orc)
+    g0, b0 = I.linear_ramp_params(2)
+    res = O.optimize_qaoa(sim, g0, b0, method="SLSQP", max_calls=40, scale=2.5)
+    for c in res.history:
+        e, _ = sim.energy(c.gamma, c.beta)
+        assert abs(e - c.energy) <= 1e-12 * orc.coeff_scale(inst)
+
+
+def test_history_json_round_trip(orc, tmp_path):
+    _, sim = small_problem(orc)
+    g0, b0 = I.linear_ramp_params(1)
+    res = O.optimize_qaoa(sim, g0, b0, method="Nelder-Mead", max_calls=12)
+    path = tmp_path / "opt.json"
+    text = res.to_json(str(path))
+    back = O.OptResult.from_json(path.read_text())
+    assert back == res
+    assert json.loads(text)["calls"] == 12
+
+
+def test_argument_checks(orc):
+    _, sim = small_problem(orc)
+    with pytest.raises(ValueError):
+        O.optimize_qaoa(sim, [0.1], [0.2, 0.3])
+    with pytest.raises(ValueError):
+        O.optimize_qaoa(sim, [0.1], [0.2], max_calls=0)
+    with pytest.raises(ValueError):
+        O.optimize_qaoa(sim, [0.1], [0.2], scale=0.0)
+    with pytest.raises(ValueError):
+        O.optimize_qaoa(sim, [0.1], [0.2], method="Nelder-Mead", use_grad=True)
+
+
+def test_second_order_init_matches_oracle_schedule(orc):
+    p, tau = 5, 0.75
+    g, b = O.second_order_init(p, tau)
+    rg, rb = orc.second_order_schedule(p, tau)
+    assert np.allclose(g, rg, rtol=0, atol=1e-15) and np.allclose(b, rb, rtol=0, atol=1e-15)
+
+
+# ----------------------------------------------------------------------------- GPU
+@pytest.mark.gpu
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_device_loop_matches_oracle_loop(orc, dtype):
+    """The same optimiser driven by the GPU and by the oracle: every call of the
+    GPU loop agrees with the oracle at the GPU's own point, and both loops reach
+    the same minimum."""
+    from paper_2104_03293_amd import sv
+    n, p = 12, 2
+    inst = I.degree4_int2(n, 21)
+    ref = OracleQAOA(orc, inst)
+    H = sv.Ising.from_instance(inst)
+    dev = O.DeviceQAOA(H, dtype)
+    g0, b0 = I.linear_ramp_params(p)
+    res = O.optimize_qaoa(dev, g0, b0, method="L-BFGS-B", max_calls=100)
+    rres = O.optimize_qaoa(ref, g0, b0, method="L-BFGS-B", max_calls=100)
+    scale = orc.coeff_scale(inst)
+    etol = 1e-6 * scale
+    ptol = 1e-11 if dtype == "c128" else 1e-6
+    for c in res.history[:: max(1, len(res.history) // 8)]:
+        e, pg = ref.energy(c.gamma, c.beta)
+        assert abs(c.energy - e) <= etol
+        assert abs(c.p_gs - pg) <= ptol
+    assert res.converged and rres.converged
+    assert abs(res.energy - rres.energy) <= etol
+    e, pg = dev.energy(res.gamma, res.beta)
+    assert abs(e - res.energy) <= etol
+    dev.close()
