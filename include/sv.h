@@ -181,6 +181,37 @@ int sv_expect(sv_state s, sv_ising H, double* energy, double* p_gs, double* norm
  * FP64 sums in a fixed order.  Synchronises the stream. */
 int sv_spin_z(sv_state s, double* out);
 
+/* --------------------------------------------------- general single-qubit layers --
+ * Apply nlayers layers of single-qubit gates: layer k applies the 2x2 complex
+ * matrix U_{k,q} to every qubit q (the gate set of the Hadamard benchmark,
+ * Sec. II.B, and the single-spin factors of Eq. AQA4).
+ *   U: host, [nlayers][n][8] doubles, row-major (u00 re, u00 im, u01 re, u01 im,
+ *      u10 re, u10 im, u11 re, u11 im); u00 maps the amplitude with bit q = 0
+ *      to itself.  Any complex matrix is accepted (unitarity is not checked).
+ *   nlayers == 0 is a no-op.  Since gates on different qubits commute, each
+ *   tile group takes up to four consecutive layers per pass over the state.
+ * SV_ERR_NUMERIC for a non-finite entry.  Asynchronous on the state's stream
+ * (U is copied before the call returns). */
+int sv_gate_layers(sv_state s, int nlayers, const double* U);
+
+/* Time stepping of Eq. AQA4 (the paper's TDSE solver for annealing): for
+ * l = 0..steps-1, with A_l = A[l], B_l = B[l] (the annealing functions sampled
+ * at the step's time, e.g. s = l/steps for t_anneal = steps * tau),
+ *   |psi> <- M_l exp(i tau sum_{i<j} Jt_ij Z_i Z_j) M_l |psi>,
+ *   M_l = prod_i exp(i tau/2 (A_l X_i + ht_i Z_i)),  ht_i = -B_l h_i,  Jt_ij = -B_l J_ij
+ * (Eqs. AQA0-AQA3: x fields A, z fields -B h, zz couplings -B J; Z has
+ * eigenvalue -1 on bit 0, Sec. III.A.3).  from_plus != 0 starts from |+>^n
+ * (the paper's initial state), else from the current state.
+ * Per-step outputs (host, may each be NULL): energy_per_step[steps] = <H_C>,
+ * pgs_per_step[steps] = ground-state probability, spinz_per_step[steps][n] =
+ * <sigma^z_i>, all after the step.  With every output NULL the outer half
+ * steps of consecutive steps are merged into one single-qubit layer (one pass
+ * per tile group and step); with outputs each step costs two layers.
+ * SV_ERR_NUMERIC for non-finite tau, A or B.  Synchronises when an output is
+ * requested. */
+int sv_qsds_run(sv_state s, sv_ising H, int steps, double tau, const double* A, const double* B,
+                int from_plus, double* energy_per_step, double* pgs_per_step, double* spinz_per_step);
+
 /* ---------------------------------------------------------------- adjoint --
  * Gradient of f(gamma, beta) = <beta,gamma| H_C |beta,gamma> with respect to
  * all 2p parameters in one reverse sweep that uncomputes the state instead of

@@ -139,6 +139,25 @@ void orc_rx(int n, int q, double beta, double* psi) {
     }
 }
 
+/* A general 2x2 complex matrix U on qubit q (row-major, interleaved re/im:
+ * u00, u01, u10, u11), Eq. twocomponentupdates with an arbitrary u:
+ * a' = u00 a + u01 b, b' = u10 a + u11 b for every pair (a, b) = (psi[z], psi[z | 2^q]). */
+void orc_gate_1q(int n, int q, const double* U, double* psi) {
+    const int64_t N = (int64_t)1 << n;
+    const int64_t bit = (int64_t)1 << q;
+#pragma omp parallel for schedule(static)
+    for (int64_t z = 0; z < N; z++) {
+        if (z & bit) continue;
+        int64_t w = z | bit;
+        double ar = psi[2 * z], ai = psi[2 * z + 1];
+        double br = psi[2 * w], bi = psi[2 * w + 1];
+        psi[2 * z] = U[0] * ar - U[1] * ai + U[2] * br - U[3] * bi;
+        psi[2 * z + 1] = U[0] * ai + U[1] * ar + U[2] * bi + U[3] * br;
+        psi[2 * w] = U[4] * ar - U[5] * ai + U[6] * br - U[7] * bi;
+        psi[2 * w + 1] = U[4] * ai + U[5] * ar + U[6] * bi + U[7] * br;
+    }
+}
+
 /* exp(-i beta H_D) = prod_q exp(-i beta sigma^x_q), qubits 0..n-1 in order. */
 void orc_mixer(int n, double beta, double* psi) {
     for (int q = 0; q < n; q++) orc_rx(n, q, beta, psi);

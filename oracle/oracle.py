@@ -48,6 +48,7 @@ def lib():
         L.orc_cost_phase.argtypes = [ctypes.c_int, _dp, ctypes.c_double, _dp]
         L.orc_rx.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, _dp]
         L.orc_mixer.argtypes = [ctypes.c_int, ctypes.c_double, _dp]
+        L.orc_gate_1q.argtypes = [ctypes.c_int, ctypes.c_int, _dp, _dp]
         L.orc_qaoa.argtypes = [ctypes.c_int, _dp, ctypes.c_int, _dp, _dp, ctypes.c_int, _dp]
         L.orc_observables.argtypes = [ctypes.c_int, _dp, _dp, ctypes.c_double, ctypes.c_double,
                                       _dp, _dp, _dp]
@@ -158,6 +159,25 @@ def mixer(n: int, psi: np.ndarray, beta: float) -> np.ndarray:
     """exp(-i beta H_D) psi, H_D = sum_i sigma^x_i."""
     out = np.array(psi, dtype=np.complex128, copy=True)
     lib().orc_mixer(n, float(beta), _d(out.view(np.float64)))
+    return out
+
+
+def gate_1q(n: int, psi: np.ndarray, q: int, U) -> np.ndarray:
+    """A 2x2 complex matrix U on qubit q (new array)."""
+    u = np.ascontiguousarray(np.asarray(U, dtype=np.complex128).reshape(2, 2)).view(np.float64).reshape(-1)
+    out = np.array(psi, dtype=np.complex128, copy=True)
+    lib().orc_gate_1q(n, int(q), _d(u), _d(out.view(np.float64)))
+    return out
+
+
+def gate_layers(n: int, psi: np.ndarray, U) -> np.ndarray:
+    """Layers of single-qubit gates, U[k, q] (2x2) on qubit q in layer k; within a
+    layer the qubits go 0..n-1 (they commute)."""
+    U = np.asarray(U, dtype=np.complex128)
+    out = np.array(psi, dtype=np.complex128, copy=True)
+    for k in range(U.shape[0]):
+        for q in range(n):
+            out = gate_1q(n, out, q, U[k, q])
     return out
 
 
@@ -331,6 +351,55 @@ def product_energy(h, gamma, beta) -> float:
     phi = product_state_factors(h, gamma, beta)
     pz = np.abs(phi[:, 1]) ** 2 - np.abs(phi[:, 0]) ** 2
     return float(np.sum(np.asarray(h, dtype=np.float64) * pz))
+
+
+# ----------------------------------------------------------------------------- QSDS time stepping
+_SX = np.array([[0.0, 1.0], [1.0, 0.0]], dtype=np.complex128)
+_SZ = np.array([[-1.0, 0.0], [0.0, 1.0]], dtype=np.complex128)   # |0> is the -1 eigenstate
+
+
+def single_spin_exponential(theta: float, hx: float, hz: float) -> np.ndarray:
+    """exp(i theta (hx sigma^x + hz sigma^z)) as a 2x2 matrix (scipy expm)."""
+    from scipy.linalg import expm
+    return expm(1j * theta * (hx * _SX + hz * _SZ))
+
+
+def coupling_phase(inst, psi: np.ndarray, angle: float) -> np.ndarray:
+    """exp(i angle sum_{i<j} J_ij sigma^z_i sigma^z_j) psi: the cost phase of the
+    instance with its fields removed, at gamma = -angle."""
+    zero = dict(inst)
+    zero["h"] = np.zeros(int(inst["n"]))
+    return cost_phase(zero, psi, -angle)
+
+
+def qsds_run(inst, tau: float, A, B, psi0=None, observe: bool = False):
+    """Eq. AQA4 for the Hamiltonian of Eqs. AQA0-AQA3: step l applies
+        exp(i tau/2 sum_i (hx sigma^x_i + hz_i sigma^z_i))
+        exp(i tau sum_{i<j} Jz_ij sigma^z_i sigma^z_j)
+        exp(i tau/2 sum_i (hx sigma^x_i + hz_i sigma^z_i))
+    with hx = A[l], hz_i = -B[l] h_i, Jz_ij = -B[l] J_ij, starting from |+>^n (or
+    psi0).  observe=True also returns per-step (<H_C>, P_gs, <sigma^z_i>)."""
+    n = int(inst["n"])
+    h = np.asarray(inst["h"], dtype=np.float64)
+    psi = plus_state(n) if psi0 is None else np.array(psi0, dtype=np.complex128)
+    E = energies(inst) if observe else None
+    gs = ground(inst, E) if observe else None
+    en, pg, sz = [], [], []
+    for a, b in zip(np.atleast_1d(A), np.atleast_1d(B)):
+        outer = [single_spin_exponential(tau / 2.0, a, -b * h[i]) for i in range(n)]
+        for i in range(n):
+            psi = gate_1q(n, psi, i, outer[i])
+        psi = coupling_phase(inst, psi, -tau * b)
+        for i in range(n):
+            psi = gate_1q(n, psi, i, outer[i])
+        if observe:
+            _, e, p = observables(inst, psi, E=E, gs=gs)
+            en.append(e)
+            pg.append(p)
+            sz.append(spin_z(n, psi))
+    if observe:
+        return psi, np.array(en), np.array(pg), np.array(sz)
+    return psi
 
 
 # ----------------------------------------------------------------------------- schedules

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -230,6 +231,9 @@ struct Work {
     size_t res_cap = 0;  // doubles
     double* d_spin = nullptr;  // per-tile spin partials [ntiles][kTF]
     size_t spin_cap = 0;       // doubles
+    double* d_gmat = nullptr;  // general single-qubit layers, kGenBlock doubles per MIX op
+    double* h_gmat = nullptr;  // pinned staging copy
+    size_t gmat_cap = 0;       // doubles
 };
 
 struct sv_state_s {
@@ -662,6 +666,7 @@ struct Event {
     double angle = 0;   // EV_PHASE gamma / EV_MIX beta
     int vec = 1;        // vectors touched (bit0 psi, bit1 lam)
     int res = -1;       // result index (REDUCE: 3 consecutive; GGAMMA; MIX grad-beta)
+    int gm = -1;        // EV_MIX: index of a general single-qubit layer (Program::layers), -1: exp(-i angle X)
 };
 
 struct Pass {
@@ -674,11 +679,14 @@ struct Pass {
     std::vector<int> slot_dst;                  // result index of each slot
     std::vector<std::pair<int, double>> phase;  // (layout, gamma) per phase table
     int spin_res = -1;                          // PT_SPINZ: first result index of the n spin expectations
+    bool gen = false;                           // its MIX ops are general single-qubit layers
 };
 
 struct Program {
     std::vector<Pass> passes;
     int nres = 0;
+    const double* layers = nullptr;  // general layers, host [layer][qubit][8] (complex 2x2, row-major)
+    int nq = 0;                      // qubits per layer
 };
 
 static int point_rank(int flags) {
@@ -728,6 +736,34 @@ static Program build_program(const std::vector<Event>& evs, int nres, bool fuse)
             cur.init = true;
             continue;
         }
+        if (e.kind == EV_MIX && e.gm >= 0) {
+            // general single-qubit layer: one op; a pass without a POINT takes up
+            // to four of them (the empty point slot is skipped)
+            bool can = open && (!cur.has_mix || (cur.group == e.group && fuse && cur.gen));
+            if (can) can = has_point ? nmix_post < 2 : (nmix_pre < 2 || nmix_post < 2);
+            if (!can) {
+                close();
+                start(e.group);
+            }
+            cur.group = e.group;
+            cur.gen = true;
+            Op op{};
+            op.kind = OP_MIX;
+            op.flags = MIX_PSI | MIX_GEN;
+            op.slot = -1;
+            op.slot2 = -1;
+            op.qidx = e.gm;
+            op.a = 0.0;
+            op.b = 1.0;
+            if (!has_point && nmix_pre < 2) {
+                cur.ops[nmix_pre++] = op;
+            } else {
+                has_point = true;  // later POINT events start a new pass
+                cur.ops[3 + nmix_post++] = op;
+            }
+            cur.has_mix = true;
+            continue;
+        }
         if (e.kind == EV_MIX) {
             // exp(-i beta X) = (-1)^k exp(-i beta' X), beta' = beta - k pi in [-pi/2, pi/2];
             // |beta'| > pi/4 is applied as two halves so that |tan| <= 1.
@@ -737,7 +773,7 @@ static Program build_program(const std::vector<Event>& evs, int nres, bool fuse)
             const int nhalf = std::fabs(bred) > M_PI / 4 ? 2 : 1;
             const double bh = bred / nhalf;
             const int slots = e.res >= 0 ? 1 : 0;
-            bool can = open && (!cur.has_mix || (cur.group == e.group && fuse)) &&
+            bool can = open && (!cur.has_mix || (cur.group == e.group && fuse && !cur.gen)) &&
                        (int)cur.slot_dst.size() + slots <= limit(e);
             if (can) {
                 if (!has_point) can = nmix_pre + nhalf <= 2;
@@ -1023,6 +1059,56 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
             return fail(SV_ERR_HIP, "table launch failed: %s", hipGetErrorString((hipError_t)e));
         }
     }
+    // general single-qubit layers: one block of kGenBlock doubles per MIX op
+    // (matrix of tile bit l at 8 l; identity for phantom bits)
+    std::vector<std::array<int, kMaxOps>> genblk(prog.passes.size());
+    size_t nblk = 0;
+    for (size_t pi = 0; pi < prog.passes.size(); pi++) {
+        genblk[pi].fill(-1);
+        for (int i = 0; i < kMaxOps; i++) {
+            const Op& op = prog.passes[pi].ops[i];
+            if (op.kind == OP_MIX && (op.flags & MIX_GEN)) genblk[pi][i] = (int)nblk++;
+        }
+    }
+    if (nblk > 0) {
+        if (!prog.layers || prog.nq != s->n) return fail(SV_ERR_ARG, "internal: general layers without matrices");
+        const size_t need = nblk * (size_t)kGenBlock;
+        // the staging buffer may still feed the previous call's copy
+        HIPCHECK(hipStreamSynchronize(s->stream));
+        if (need > s->w.gmat_cap) {
+            if (s->w.d_gmat) (void)hipFree(s->w.d_gmat);
+            if (s->w.h_gmat) (void)hipHostFree(s->w.h_gmat);
+            s->w.d_gmat = nullptr;
+            s->w.h_gmat = nullptr;
+            s->w.gmat_cap = 0;
+            HIPCHECK(hipMalloc(&s->w.d_gmat, need * sizeof(double)));
+            HIPCHECK(hipHostMalloc(&s->w.h_gmat, need * sizeof(double), hipHostMallocDefault));
+            s->w.gmat_cap = need;
+        }
+        for (size_t pi = 0; pi < prog.passes.size(); pi++) {
+            const Geometry& geo = plan.by_nv[prog.passes[pi].nv][prog.passes[pi].group];
+            for (int i = 0; i < kMaxOps; i++) {
+                if (genblk[pi][i] < 0) continue;
+                double* blk = s->w.h_gmat + (size_t)genblk[pi][i] * kGenBlock;
+                const int layer = prog.passes[pi].ops[i].qidx;
+                for (int l = 0; l < kGenBlock / 8; l++) {
+                    const int q = l < geo.T ? global_bit(geo, l) : -1;
+                    if (q < 0) {
+                        const double id[8] = {1, 0, 0, 0, 0, 0, 1, 0};
+                        memcpy(blk + 8 * l, id, sizeof(id));
+                    } else {
+                        memcpy(blk + 8 * l, prog.layers + ((size_t)layer * s->n + q) * 8, 8 * sizeof(double));
+                    }
+                }
+            }
+        }
+        hipError_t e = hipMemcpyAsync(s->w.d_gmat, s->w.h_gmat, need * sizeof(double), hipMemcpyHostToDevice,
+                                      s->stream);
+        if (e != hipSuccess) {
+            s->failed = true;
+            return fail(SV_ERR_HIP, "hipMemcpyAsync (layer matrices): %s", hipGetErrorString(e));
+        }
+    }
     const int ntmin = knob_for("ntmin", (int)s->dt, s->n);
     const int persist = knob_for("persist", (int)s->dt, s->n);
     const int stagger = knob_for("stagger", (int)s->dt, s->n);
@@ -1077,7 +1163,11 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         a.emin = emin;
         a.etol = etol;
         a.amp0 = amp0;
-        for (int i = 0; i < kMaxOps; i++) a.ops[i] = p.ops[i];
+        for (int i = 0; i < kMaxOps; i++) {
+            a.ops[i] = p.ops[i];
+            if (genblk[pi][i] >= 0) a.ops[i].qidx = genblk[pi][i];
+        }
+        a.gmat = p.gen ? s->w.d_gmat : nullptr;
         hipEvent_t ev0;
         const bool prof = prof_begin(s->stream, &ev0);
         int e = launch_pass((int)s->dt, p.nv, geo.T, a, s->stream);
@@ -1186,6 +1276,8 @@ extern "C" int sv_free(sv_state s) {
     if (s->owned && s->ptr) (void)hipFree(s->ptr);
     if (s->w.d_part) (void)hipFree(s->w.d_part);
     if (s->w.d_spin) (void)hipFree(s->w.d_spin);
+    if (s->w.d_gmat) (void)hipFree(s->w.d_gmat);
+    if (s->w.h_gmat) (void)hipHostFree(s->w.h_gmat);
     if (s->w.d_tab) (void)hipFree(s->w.d_tab);
     if (s->w.d_res) (void)hipFree(s->w.d_res);
     if (s->w.h_res) (void)hipHostFree(s->w.h_res);
@@ -1650,6 +1742,189 @@ extern "C" int sv_spin_z(sv_state s, double* out) {
     rc = fetch_results(s, s->n);
     if (rc) return rc;
     for (int i = 0; i < s->n; i++) out[i] = s->w.h_res[i];
+    return SV_OK;
+}
+
+// ============================================================================ general layers
+// Events of one general single-qubit layer: every tile group once, in snake order.
+static void push_layer(std::vector<Event>& ev, const std::vector<int>& order, int layer, bool reversed) {
+    const int ng = (int)order.size();
+    for (int i = 0; i < ng; i++) {
+        Event e{EV_MIX};
+        e.group = order[reversed ? ng - 1 - i : i];
+        e.gm = layer;
+        ev.push_back(e);
+    }
+}
+
+extern "C" int sv_gate_layers(sv_state s, int nlayers, const double* U) {
+    if (!s) return fail(SV_ERR_ARG, "sv_gate_layers: NULL state");
+    if (nlayers < 0) return fail(SV_ERR_ARG, "sv_gate_layers: nlayers=%d < 0", nlayers);
+    if (nlayers == 0) return SV_OK;
+    if (!U) return fail(SV_ERR_ARG, "sv_gate_layers: NULL matrices");
+    const size_t cnt = (size_t)nlayers * s->n * 8;
+    for (size_t i = 0; i < cnt; i++)
+        if (!std::isfinite(U[i]))
+            return fail(SV_ERR_NUMERIC, "sv_gate_layers: non-finite entry in layer %d, qubit %d", (int)(i / 8 / s->n),
+                        (int)(i / 8 % s->n));
+    Plan plan = make_plan(s->n, s->dt);
+    const std::vector<int> order = group_order((int)plan.by_nv[1].size(), (int)s->dt, s->n);
+    const int ng = (int)order.size();
+    // Gates on different qubits commute, so each tile group takes up to four
+    // consecutive layers in one pass (the pass shape has four mixer slots).
+    std::vector<Event> ev;
+    for (int c0 = 0; c0 < nlayers; c0 += 4) {
+        const int c1 = std::min(nlayers, c0 + 4);
+        for (int gi = 0; gi < ng; gi++) {
+            for (int l = c0; l < c1; l++) {
+                Event e{EV_MIX};
+                e.group = order[gi];
+                e.gm = l;
+                ev.push_back(e);
+            }
+        }
+    }
+    Program prog = build_program(ev, 0, true);
+    prog.layers = U;
+    prog.nq = s->n;
+    return run_program(s, nullptr, nullptr, prog, plan, false);
+}
+
+// exp(i theta (a X + c Z)) with Z = diag(-1, +1) (the paper's |0> is the -1
+// eigenstate): cos(theta r) I + i sin(theta r) / r (a X + c Z), r = |(a, c)|.
+static void spin_exp(double theta, double a, double c, double m[8]) {
+    const double r = std::hypot(a, c);
+    const double cs = std::cos(theta * r);
+    const double sr = r > 0.0 ? std::sin(theta * r) / r : theta;
+    const double v[8] = {cs, -sr * c, 0.0, sr * a, 0.0, sr * a, cs, sr * c};
+    memcpy(m, v, sizeof(v));
+}
+
+// 2x2 complex product out = x y (row-major, interleaved re/im).
+static void mat_mul(const double* x, const double* y, double* out) {
+    double o[8];
+    for (int i = 0; i < 2; i++)
+        for (int j = 0; j < 2; j++) {
+            double re = 0.0, im = 0.0;
+            for (int k = 0; k < 2; k++) {
+                const double ar = x[(2 * i + k) * 2], ai = x[(2 * i + k) * 2 + 1];
+                const double br = y[(2 * k + j) * 2], bi = y[(2 * k + j) * 2 + 1];
+                re += ar * br - ai * bi;
+                im += ar * bi + ai * br;
+            }
+            o[(2 * i + j) * 2] = re;
+            o[(2 * i + j) * 2 + 1] = im;
+        }
+    memcpy(out, o, sizeof(o));
+}
+
+// Second-order product-formula time stepping of Eq. AQA4 for the annealing
+// Hamiltonian of Eqs. AQA0-AQA3 (x fields A, z fields -B h_i, zz couplings -B J_ij):
+// step l applies M_l P_J(tau B_l) M_l with M_l = prod_i exp(i tau/2 (A_l X_i - B_l h_i Z_i))
+// and P_J(gamma) = exp(-i gamma sum_{i<j} J_ij s_i s_j).  On the device P_J is the cost
+// phase exp(-i gamma E) times the diagonal exp(+i gamma sum_i h_i s_i), which is folded
+// into the single-qubit matrix beside it: N_l = D_l M_l.  Without per-step observables the
+// outer halves of consecutive steps merge, so a step costs one general layer and one phase.
+extern "C" int sv_qsds_run(sv_state s, sv_ising H, int steps, double tau, const double* A, const double* B,
+                           int from_plus, double* energy_per_step, double* pgs_per_step, double* spinz_per_step) {
+    int rc = check_pair(s, H, "sv_qsds_run");
+    if (rc) return rc;
+    if (steps < 1) return fail(SV_ERR_ARG, "sv_qsds_run: steps=%d < 1", steps);
+    if (!A || !B) return fail(SV_ERR_ARG, "sv_qsds_run: NULL schedule array");
+    if (!std::isfinite(tau)) return fail(SV_ERR_NUMERIC, "sv_qsds_run: tau is not finite");
+    for (int l = 0; l < steps; l++)
+        if (!std::isfinite(A[l]) || !std::isfinite(B[l]))
+            return fail(SV_ERR_NUMERIC, "sv_qsds_run: non-finite schedule value at step %d", l);
+    const int n = s->n;
+    const bool want = energy_per_step || pgs_per_step;
+    const bool spins = spinz_per_step != nullptr;
+    const bool observe = want || spins;
+    std::vector<double> Mh((size_t)steps * n * 8), Nh((size_t)steps * n * 8);
+    for (int l = 0; l < steps; l++) {
+        const double gam = tau * B[l];
+        for (int i = 0; i < n; i++) {
+            double* m = &Mh[((size_t)l * n + i) * 8];
+            double* nn = &Nh[((size_t)l * n + i) * 8];
+            spin_exp(0.5 * tau, A[l], -B[l] * H->h[i], m);
+            // D = diag(exp(-i gam h_i), exp(+i gam h_i)) times M: scale the rows
+            const double c = std::cos(gam * H->h[i]), sn = std::sin(gam * H->h[i]);
+            for (int row = 0; row < 2; row++) {
+                const double dr = c, di = row == 0 ? -sn : sn;
+                for (int col = 0; col < 2; col++) {
+                    const double xr = m[(2 * row + col) * 2], xi = m[(2 * row + col) * 2 + 1];
+                    nn[(2 * row + col) * 2] = dr * xr - di * xi;
+                    nn[(2 * row + col) * 2 + 1] = dr * xi + di * xr;
+                }
+            }
+        }
+    }
+    // layer list and events
+    std::vector<double> layers;
+    auto add_layer = [&](const double* src) { layers.insert(layers.end(), src, src + (size_t)n * 8); };
+    Plan plan = make_plan(n, s->dt);
+    const std::vector<int> order = group_order((int)plan.by_nv[1].size(), (int)s->dt, n);
+    std::vector<Event> ev;
+    if (from_plus) ev.push_back(Event{EV_INIT});
+    int nl = 0;
+    auto layer_events = [&]() {
+        push_layer(ev, order, nl, (nl % 2) == 1);
+        nl++;
+    };
+    auto phase = [&](int l) {
+        Event ph{EV_PHASE};
+        ph.angle = tau * B[l];
+        ev.push_back(ph);
+    };
+    const int nres = (want ? 3 * steps : 0) + (spins ? steps * n : 0);
+    if (!observe) {
+        add_layer(&Nh[0]);
+        layer_events();
+        std::vector<double> prod((size_t)n * 8);
+        for (int l = 0; l < steps; l++) {
+            phase(l);
+            if (l + 1 < steps) {
+                for (int i = 0; i < n; i++)
+                    mat_mul(&Nh[((size_t)(l + 1) * n + i) * 8], &Mh[((size_t)l * n + i) * 8], &prod[(size_t)i * 8]);
+                add_layer(prod.data());
+            } else {
+                add_layer(&Mh[(size_t)l * n * 8]);
+            }
+            layer_events();
+        }
+    } else {
+        for (int l = 0; l < steps; l++) {
+            add_layer(&Nh[(size_t)l * n * 8]);
+            layer_events();
+            phase(l);
+            add_layer(&Mh[(size_t)l * n * 8]);
+            layer_events();
+            if (want) {
+                Event r{EV_REDUCE};
+                r.res = 3 * l;
+                ev.push_back(r);
+            }
+            if (spins) {
+                Event sz{EV_SPINZ};
+                sz.res = (want ? 3 * steps : 0) + l * n;
+                ev.push_back(sz);
+            }
+        }
+    }
+    Program prog = build_program(ev, nres, knob_for("fuse", (int)s->dt, n) != 0);
+    prog.layers = layers.data();
+    prog.nq = n;
+    rc = run_program(s, nullptr, H, prog, plan, want);
+    if (rc || nres == 0) return rc;
+    rc = fetch_results(s, nres);
+    if (rc) return rc;
+    for (int l = 0; l < steps; l++) {
+        if (energy_per_step) energy_per_step[l] = s->w.h_res[3 * l + 1];
+        if (pgs_per_step) pgs_per_step[l] = s->w.h_res[3 * l + 2];
+    }
+    if (spins) {
+        const double* sp = s->w.h_res + (want ? 3 * steps : 0);
+        for (int k = 0; k < steps * n; k++) spinz_per_step[k] = sp[k];
+    }
     return SV_OK;
 }
 

@@ -39,7 +39,14 @@ enum OpKind : int32_t { OP_MIX = 1, OP_POINT = 2 };
 // a = tan(beta') for |beta'| <= pi/4, and multiplies the vector's uniform
 // pending scale by b = +-cos(beta') per qubit (the host reduces beta modulo pi
 // and splits larger angles into two halves).
-enum MixFlags : int32_t { MIX_PSI = 1, MIX_LAM = 2, MIX_GBETA = 4 };
+enum MixFlags : int32_t { MIX_PSI = 1, MIX_LAM = 2, MIX_GBETA = 4, MIX_GEN = 8 };
+
+// MIX_GEN (one-vector passes): a general single-qubit layer instead.  Every
+// active tile bit l gets its own complex 2x2 matrix m, (u, v) <- (m00 u + m01 v,
+// m10 u + m11 v), read from PassArgs::gmat + qidx * kGenBlock + 8 l as
+// (m00 re, im, m01 re, im, m10 re, im, m11 re, im); u is the amplitude whose
+// bit is 0.
+constexpr int kGenBlock = 16 * 8;
 
 // POINT flags, executed in this order.
 enum PointFlags : int32_t {
@@ -152,6 +159,7 @@ struct PassArgs {
     int32_t lut_half;       // L of the phase tables (in units of 1/q), -1 for other real-valued instances
     double lut_q;           // q: table index = q * energy
     double* spin_part;      // [ntiles][kTF] spin partials (passes with PT_SPINZ)
+    const double* gmat;     // general single-qubit layers (passes whose MIX ops carry MIX_GEN), else null
     uint32_t qph_off[kMaxPhase];
     uint32_t lut_off[kMaxPhase];
     double emin, etol;      // ground-state test |E - emin| <= etol

@@ -62,6 +62,8 @@ def _load():
         "sv_aqa_run_observe": (ip, [vp, vp, ip, dp, dp, dp, dp, dp]),
         "sv_spin_z": (ip, [vp, dp]),
         "sv_expect": (ip, [vp, vp, dp, dp, dp]),
+        "sv_gate_layers": (ip, [vp, ip, dp]),
+        "sv_qsds_run": (ip, [vp, vp, ip, ctypes.c_double, dp, dp, ip, dp, dp, dp]),
         "sv_grad": (ip, [vp, vp, vp, ip, dp, dp, ip, dp, dp, dp, dp]),
         "sv_schedule_linear": (ip, [ip, ctypes.c_double, ip, dp, dp]),
         "sv_schedule_second_order": (ip, [ip, ctypes.c_double, dp, dp, dp, dp]),
@@ -307,6 +309,35 @@ def spin_z(s: State) -> np.ndarray:
     out = np.empty(s.n)
     _check(lib.sv_spin_z(s.handle, _dp(out)))
     return out
+
+
+def gate_layers(s: State, U) -> None:
+    """Apply single-qubit gate layers: U has shape (layers, n, 2, 2) complex
+    (layer k applies U[k, q] to qubit q)."""
+    U = np.asarray(U, dtype=np.complex128)
+    if U.ndim != 4 or U.shape[1:] != (s.n, 2, 2):
+        raise ValueError(f"U must have shape (layers, {s.n}, 2, 2)")
+    flat = np.ascontiguousarray(U).view(np.float64).reshape(-1)
+    _check(lib.sv_gate_layers(s.handle, U.shape[0], _dp(flat)))
+
+
+def qsds_run(s: State, H: Ising, tau: float, A, B, from_plus: bool = True, observe: bool = False):
+    """Eq. AQA4 time stepping with the annealing samples A[l], B[l]; with
+    observe=True returns per-step (<H_C>[steps], P_gs[steps], <sigma^z>[steps, n])."""
+    a, b = _f64(A), _f64(B)
+    if len(a) != len(b):
+        raise ValueError("A and B must have equal length")
+    if observe:
+        en = np.empty(len(a))
+        pg = np.empty(len(a))
+        sz = np.empty((len(a), s.n))
+        _check(lib.sv_qsds_run(s.handle, H.handle, len(a), float(tau), _dp(a), _dp(b), int(bool(from_plus)),
+                               _dp(en), _dp(pg), _dp(sz)))
+        return en, pg, sz
+    null = ctypes.POINTER(ctypes.c_double)()
+    _check(lib.sv_qsds_run(s.handle, H.handle, len(a), float(tau), _dp(a), _dp(b), int(bool(from_plus)), null, null,
+                           null))
+    return None
 
 
 def expect(s: State, H: Ising):

@@ -128,6 +128,17 @@ def test_state_validation(sv):
     st = out
     assert sv.lib.sv_mixer(st, ctypes.c_double(float("nan"))) == 5
     assert sv.lib.sv_copy_to_host(st, ctypes.c_void_p(4096), 12) == 1  # byte count mismatch
+    # general layers: argument checks come before any GPU work
+    U = np.zeros(10 * 8)
+    U[0] = np.inf
+    dp = ctypes.POINTER(ctypes.c_double)
+    assert sv.lib.sv_gate_layers(st, -1, U.ctypes.data_as(dp)) == 1
+    assert sv.lib.sv_gate_layers(st, 1, None) == 1
+    assert sv.lib.sv_gate_layers(st, 1, U.ctypes.data_as(dp)) == 5
+    assert sv.lib.sv_gate_layers(st, 0, None) == 0
+    assert sv.lib.sv_gate_layers(None, 1, U.ctypes.data_as(dp)) == 1
+    assert sv.lib.sv_qsds_run(st, None, 1, ctypes.c_double(0.5), U.ctypes.data_as(dp), U.ctypes.data_as(dp), 1,
+                              None, None, None) == 1
     assert sv.lib.sv_free(st) == 0
 
 

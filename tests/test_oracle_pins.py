@@ -389,3 +389,95 @@ def test_gradient_single_qubit_analytic(orc):
     f, dg, db = orc.grad_tangent(inst, [g], [b])
     assert abs(dg[0] - 2 * h * h * math.cos(2 * g * h) * math.sin(2 * b)) < 1e-14
     assert abs(db[0] - 2 * h * math.sin(2 * g * h) * math.cos(2 * b)) < 1e-14
+
+
+# ----------------------------------------------------------------------------- general layers, Eq. AQA4
+def _random_2x2(rng):
+    return rng.normal(size=(2, 2)) + 1j * rng.normal(size=(2, 2))
+
+
+def test_gate_layers_vs_kronecker_products(orc):
+    """Each gate acts as I x .. x U x .. x I with qubit 0 the last factor (Sec. II.A);
+    any complex 2x2, not only unitaries."""
+    n, nl = 5, 3
+    rng = np.random.default_rng(71)
+    U = np.array([[_random_2x2(rng) for _ in range(n)] for _ in range(nl)])
+    psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    ref = psi.copy()
+    for k in range(nl):
+        for q in range(n):
+            ref = dense.single(n, q, U[k, q]) @ ref
+    assert np.max(np.abs(orc.gate_layers(n, psi, U) - ref)) < 1e-12 * np.max(np.abs(ref))
+
+
+def test_hadamard_benchmark_circuit(orc):
+    """(H^{xN})^{11} (Sec. II.B): H is an involution, so eleven layers equal one, and
+    from |0...0> the result is the uniform superposition."""
+    n = 7
+    Hm = np.array([[1, 1], [1, -1]], dtype=np.complex128) / math.sqrt(2.0)
+    U = np.broadcast_to(Hm, (11, n, 2, 2))
+    zero = np.zeros(1 << n, dtype=np.complex128)
+    zero[0] = 1.0
+    out = orc.gate_layers(n, zero, U)
+    assert np.max(np.abs(out - 2.0 ** (-n / 2))) < 1e-13
+    rng = np.random.default_rng(5)
+    psi = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    one = orc.gate_layers(n, psi, U[:1])
+    assert np.max(np.abs(orc.gate_layers(n, psi, U) - one)) < 1e-12 * np.max(np.abs(psi))
+
+
+def test_single_spin_exponential_closed_form(orc):
+    """exp(i t (a X + c Z)) = cos(t r) I + i sin(t r)/r (a X + c Z), r = |(a, c)|,
+    with Z = diag(-1, 1) in the paper's labelling."""
+    for t, a, c in [(0.3, 1.0, 0.5), (1.7, -0.2, 2.5), (0.4, 0.0, -1.0), (0.9, 1.3, 0.0)]:
+        r = math.hypot(a, c)
+        ref = math.cos(t * r) * np.eye(2) + 1j * math.sin(t * r) / r * (a * dense.X + c * dense.Z_PAPER)
+        assert np.max(np.abs(orc.single_spin_exponential(t, a, c) - ref)) < 1e-14
+
+
+def test_qsds_special_cases(orc):
+    """A = 0: every factor is diagonal and the step is exp(-i tau B H_C) exactly.
+    B = 0: the step is exp(i tau A sum X) exactly, i.e. the mixer at beta = -tau A."""
+    inst = I.regular3_pm1(8, 12)
+    n, tau = 8, 0.23
+    B = np.array([0.2, 0.5, 0.9])
+    psi = orc.qsds_run(inst, tau, np.zeros(3), B)
+    ref = orc.cost_phase(inst, orc.plus_state(n), tau * B.sum())
+    assert np.max(np.abs(psi - ref)) < 1e-13
+    A = np.array([0.7, 0.4])
+    rng = np.random.default_rng(8)
+    psi0 = rng.normal(size=1 << n) + 1j * rng.normal(size=1 << n)
+    psi0 /= np.linalg.norm(psi0)
+    out = orc.qsds_run(inst, tau, A, np.zeros(2), psi0=psi0)
+    assert np.max(np.abs(out - orc.mixer(n, psi0, -tau * A.sum()))) < 1e-13
+
+
+def test_qsds_second_order_convergence_to_the_tdse(orc):
+    """With constant A, B the product formula of Eq. AQA4 approaches the exact
+    evolution exp(-i t H) under H = -sum (h~ sigma + J~ sigma sigma) of Eqs. AQA0-AQA3,
+    i.e. H = -A sum X + B H_C (= A H_I + B H_C, Eq. Hofs), with error O(tau^2)."""
+    from scipy.linalg import expm
+    inst = I.degree4_int2(6, 13)
+    n, T, A, B = 6, 1.2, 0.8, 0.35
+    Hm = -A * dense.h_driver(n) + B * dense.h_cost(inst)
+    exact = expm(-1j * T * Hm) @ dense.plus(n)
+    errs = []
+    for steps in (8, 16, 32):
+        tau = T / steps
+        psi = orc.qsds_run(inst, tau, np.full(steps, A), np.full(steps, B))
+        errs.append(np.linalg.norm(psi - exact))
+    assert errs[0] > errs[1] > errs[2]
+    for e0, e1 in zip(errs, errs[1:]):
+        assert 3.6 < e0 / e1 < 4.4
+
+
+def test_qsds_observables_per_step(orc):
+    inst = I.degree4_int2(7, 14)
+    A = np.array([0.9, 0.6, 0.3])
+    B = np.array([0.1, 0.4, 0.7])
+    psi, en, pg, sz = orc.qsds_run(inst, 0.4, A, B, observe=True)
+    psi2 = orc.qsds_run(inst, 0.4, A[:2], B[:2])
+    _, e2, p2 = orc.observables(inst, psi2)
+    assert abs(en[1] - e2) < 1e-12 and abs(pg[1] - p2) < 1e-14
+    assert np.max(np.abs(sz[-1] - orc.spin_z(7, psi))) < 1e-14
+    assert np.array_equal(psi, orc.qsds_run(inst, 0.4, A, B))
