@@ -164,6 +164,39 @@ def main():
                                  "rescale_r": rx, "energy_plus_C": ox[0] * 1.0 + Cx, "p_gs": ox[1]}
         log(f"[bench] exact cover {msx:.3f} ms/step")
         del Hx
+        # Hadamard benchmark circuit (H^{xN})^{11} (general single-qubit layers)
+        had = np.array([[1, 1], [1, -1]], dtype=np.complex128) / np.sqrt(2.0)
+        U = np.ascontiguousarray(np.broadcast_to(had, (11, n, 2, 2)))
+        sv.init_plus(s)
+        sv.profile_enable(True)
+        sv.profile_report()
+        sv.gate_layers(s, U)
+        torch.cuda.synchronize()
+        reps = 3
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sv.gate_layers(s, U)
+        torch.cuda.synchronize()
+        msh = (time.perf_counter() - t0) * 1e3 / reps
+        ph = sv.profile_report().get(f"pass_{args.dtype}_nv1", {"launches": 0, "ms": 0.0, "bytes": 0.0})
+        sv.profile_enable(False)
+        extras["hadamard"] = {"ms_per_circuit": round(msh, 3), "gates": 11 * n,
+                              "gates_per_s": 11 * n / (msh * 1e-3),
+                              "passes": ph["launches"] / (reps + 1),
+                              "pass_GBps": ph["bytes"] / (ph["ms"] * 1e-3) / 1e9 if ph["ms"] > 0 else None}
+        log(f"[bench] hadamard circuit {msh:.3f} ms")
+        # Eq. AQA4 time stepping, 10 steps of the annealing Hamiltonian, no per-step observables
+        st = 10
+        sg = np.arange(st) / st
+        sv.qsds_run(s, H, 0.5, 1.0 - sg, sg)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            sv.qsds_run(s, H, 0.5, 1.0 - sg, sg)
+        torch.cuda.synchronize()
+        msq = (time.perf_counter() - t0) * 1e3 / reps
+        extras["qsds"] = {"steps": st, "ms_per_run": round(msq, 3), "ms_per_step": round(msq / st, 3)}
+        log(f"[bench] qsds {msq:.3f} ms for {st} steps")
         # optimisation loop of the paper (SLSQP, 200-call cap) at n = 26, p = 4:
         # adjoint gradients against scipy's finite differences of energy calls
         from paper_2104_03293_amd import optimize as O

@@ -334,10 +334,9 @@ def product_state_factors(h, gamma, beta) -> np.ndarray:
     return phi
 
 
-def product_amplitudes(h, gamma, beta, zs) -> np.ndarray:
-    """Amplitudes psi(z) = prod_i phi_i[bit_i(z)] of the J = 0 state at the
-    basis indices zs (any n, no state vector)."""
-    phi = product_state_factors(h, gamma, beta)
+def factor_amplitudes(phi, zs) -> np.ndarray:
+    """Amplitudes psi(z) = prod_i phi_i[bit_i(z)] of a product state at the basis
+    indices zs (any n, no state vector)."""
     zs = np.asarray(zs, dtype=np.uint64)
     out = np.ones(len(zs), dtype=np.complex128)
     for i in range(phi.shape[0]):
@@ -346,11 +345,33 @@ def product_amplitudes(h, gamma, beta, zs) -> np.ndarray:
     return out
 
 
-def product_energy(h, gamma, beta) -> float:
-    """<H_C> = sum_i h_i (|phi_i[1]|^2 - |phi_i[0]|^2) of the J = 0 state."""
-    phi = product_state_factors(h, gamma, beta)
+def factor_energy(h, phi) -> float:
+    """<H_C> = sum_i h_i (|phi_i[1]|^2 - |phi_i[0]|^2) of a product state (J = 0)."""
     pz = np.abs(phi[:, 1]) ** 2 - np.abs(phi[:, 0]) ** 2
     return float(np.sum(np.asarray(h, dtype=np.float64) * pz))
+
+
+def product_amplitudes(h, gamma, beta, zs) -> np.ndarray:
+    """Amplitudes of the J = 0 QAOA state at the basis indices zs."""
+    return factor_amplitudes(product_state_factors(h, gamma, beta), zs)
+
+
+def product_energy(h, gamma, beta) -> float:
+    """<H_C> of the J = 0 QAOA state."""
+    return factor_energy(h, product_state_factors(h, gamma, beta))
+
+
+def qsds_product_factors(h, tau, A, B) -> np.ndarray:
+    """Single-qubit factors of the Eq. AQA4 state when all couplings vanish: the
+    zz exponential is the identity, so each step acts on qubit i alone as the
+    outer factor exp(i tau/2 (A X - B h_i Z)) applied twice.  phi[i, b], shape (n, 2)."""
+    h = np.asarray(h, dtype=np.float64)
+    phi = np.full((len(h), 2), 1.0 / math.sqrt(2.0), dtype=np.complex128)
+    for a, b in zip(np.atleast_1d(A), np.atleast_1d(B)):
+        for i in range(len(h)):
+            m = single_spin_exponential(tau / 2.0, a, -b * h[i])
+            phi[i] = m @ (m @ phi[i])
+    return phi
 
 
 # ----------------------------------------------------------------------------- QSDS time stepping

@@ -1062,6 +1062,7 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
     // general single-qubit layers: one block of kGenBlock doubles per MIX op
     // (matrix of tile bit l at 8 l; identity for phantom bits)
     std::vector<std::array<int, kMaxOps>> genblk(prog.passes.size());
+    std::vector<std::array<bool, kMaxOps>> genreal(prog.passes.size());  // every matrix of the op is real
     size_t nblk = 0;
     for (size_t pi = 0; pi < prog.passes.size(); pi++) {
         genblk[pi].fill(-1);
@@ -1091,6 +1092,7 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
                 if (genblk[pi][i] < 0) continue;
                 double* blk = s->w.h_gmat + (size_t)genblk[pi][i] * kGenBlock;
                 const int layer = prog.passes[pi].ops[i].qidx;
+                bool real = true;
                 for (int l = 0; l < kGenBlock / 8; l++) {
                     const int q = l < geo.T ? global_bit(geo, l) : -1;
                     if (q < 0) {
@@ -1099,7 +1101,9 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
                     } else {
                         memcpy(blk + 8 * l, prog.layers + ((size_t)layer * s->n + q) * 8, 8 * sizeof(double));
                     }
+                    for (int c = 1; c < 8; c += 2) real = real && blk[8 * l + c] == 0.0;
                 }
+                genreal[pi][i] = real;
             }
         }
         hipError_t e = hipMemcpyAsync(s->w.d_gmat, s->w.h_gmat, need * sizeof(double), hipMemcpyHostToDevice,
@@ -1168,6 +1172,9 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
             if (genblk[pi][i] >= 0) a.ops[i].qidx = genblk[pi][i];
         }
         a.gmat = p.gen ? s->w.d_gmat : nullptr;
+        a.gen_real = 1;
+        for (int i = 0; i < kMaxOps; i++)
+            if (genblk[pi][i] >= 0 && !genreal[pi][i]) a.gen_real = 0;
         hipEvent_t ev0;
         const bool prof = prof_begin(s->stream, &ev0);
         int e = launch_pass((int)s->dt, p.nv, geo.T, a, s->stream);

@@ -160,6 +160,7 @@ struct PassArgs {
     double lut_q;           // q: table index = q * energy
     double* spin_part;      // [ntiles][kTF] spin partials (passes with PT_SPINZ)
     const double* gmat;     // general single-qubit layers (passes whose MIX ops carry MIX_GEN), else null
+    int32_t gen_real;       // every general layer of the pass is real
     uint32_t qph_off[kMaxPhase];
     uint32_t lut_off[kMaxPhase];
     double emin, etol;      // ground-state test |E - emin| <= etol

@@ -304,30 +304,43 @@ __device__ __forceinline__ double uniform_ld(const double* p) {
 
 // General single-qubit layer, register slots: slot k holds tile bit
 // (rbpack >> 4k) & 15 and applies that bit's matrix M[l] to every register
-// pair (bit k = 0, bit k = 1).  act is uniform, so inactive slots branch away.
-template <typename Real, int R>
+// pair (bit k = 0, bit k = 1).  Inactive slots read the identity entry of tile
+// bit 15 (never a qubit of a 13- or 14-bit tile), which keeps the code
+// branch-free.  REALM: every matrix is real (two FMAs per amplitude instead
+// of eight).
+template <typename Real, int R, bool REALM>
 __device__ __forceinline__ void gen_round(Real (&vr)[1][1 << R], Real (&vi)[1][1 << R], int act, uint32_t rbpack,
                                           const double* __restrict__ M) {
     constexpr int NR = 1 << R;
 #pragma unroll
     for (int k = 0; k < R; k++) {
-        // inactive slots read the identity block entry (tile bit 15 is never a real qubit bit
-        // of a 13- or 14-bit tile, and its matrix is the identity)
         const bool on = (act >> k) & 1;
         const double* m = M + 8 * (on ? ((rbpack >> (4 * k)) & 15u) : 15u);
-        const Real a0 = (Real)uniform_ld(m), a1 = (Real)uniform_ld(m + 1);
-        const Real b0 = (Real)uniform_ld(m + 2), b1 = (Real)uniform_ld(m + 3);
-        const Real c0 = (Real)uniform_ld(m + 4), c1 = (Real)uniform_ld(m + 5);
-        const Real d0 = (Real)uniform_ld(m + 6), d1 = (Real)uniform_ld(m + 7);
+        const Real a0 = (Real)uniform_ld(m), b0 = (Real)uniform_ld(m + 2);
+        const Real c0 = (Real)uniform_ld(m + 4), d0 = (Real)uniform_ld(m + 6);
+        Real a1 = 0, b1 = 0, c1 = 0, d1 = 0;
+        if constexpr (!REALM) {
+            a1 = (Real)uniform_ld(m + 1);
+            b1 = (Real)uniform_ld(m + 3);
+            c1 = (Real)uniform_ld(m + 5);
+            d1 = (Real)uniform_ld(m + 7);
+        }
 #pragma unroll
         for (int r = 0; r < NR; r++) {
             if (r & (1 << k)) continue;
             const int r2 = r | (1 << k);
             const Real ur = vr[0][r], ui = vi[0][r], wr = vr[0][r2], wi = vi[0][r2];
-            vr[0][r] = fma(a0, ur, fma(-a1, ui, fma(b0, wr, -b1 * wi)));
-            vi[0][r] = fma(a0, ui, fma(a1, ur, fma(b0, wi, b1 * wr)));
-            vr[0][r2] = fma(c0, ur, fma(-c1, ui, fma(d0, wr, -d1 * wi)));
-            vi[0][r2] = fma(c0, ui, fma(c1, ur, fma(d0, wi, d1 * wr)));
+            if constexpr (REALM) {
+                vr[0][r] = fma(a0, ur, b0 * wr);
+                vi[0][r] = fma(a0, ui, b0 * wi);
+                vr[0][r2] = fma(c0, ur, d0 * wr);
+                vi[0][r2] = fma(c0, ui, d0 * wi);
+            } else {
+                vr[0][r] = fma(a0, ur, fma(-a1, ui, fma(b0, wr, -b1 * wi)));
+                vi[0][r] = fma(a0, ui, fma(a1, ur, fma(b0, wi, b1 * wr)));
+                vr[0][r2] = fma(c0, ur, fma(-c1, ui, fma(d0, wr, -d1 * wi)));
+                vi[0][r2] = fma(c0, ui, fma(c1, ur, fma(d0, wi, d1 * wr)));
+            }
         }
     }
 }
@@ -335,21 +348,26 @@ __device__ __forceinline__ void gen_round(Real (&vr)[1][1 << R], Real (&vi)[1][1
 // General single-qubit layer, lane bit POS (the partner lane is lane ^ 2^POS):
 // the lane whose bit is 0 holds u and forms m00 u + m01 v, its partner forms
 // m10 u + m11 v.  l is the tile bit of that lane position.
-template <int CTRL, int POS, typename Real, int R>
+template <int CTRL, int POS, typename Real, int R, bool REALM>
 __device__ __forceinline__ void gen_lane(Real (&vr)[1][1 << R], Real (&vi)[1][1 << R], int l,
                                          const double* __restrict__ M) {
     constexpr int NR = 1 << R;
     const double* m = M + 8 * l;
     const bool hi = ((threadIdx.x >> POS) & 1u) != 0;
-    const Real sr = (Real)(hi ? uniform_ld(m + 6) : uniform_ld(m)), si = (Real)(hi ? uniform_ld(m + 7) : uniform_ld(m + 1));
-    const Real orr = (Real)(hi ? uniform_ld(m + 4) : uniform_ld(m + 2));
-    const Real oi = (Real)(hi ? uniform_ld(m + 5) : uniform_ld(m + 3));
+    const int o = hi ? 6 : 0, x = hi ? 4 : 2;
+    const Real sr = (Real)m[o], orr = (Real)m[x];
+    const Real si = REALM ? (Real)0 : (Real)m[o + 1], oi = REALM ? (Real)0 : (Real)m[x + 1];
 #pragma unroll
     for (int r = 0; r < NR; r++) {
         const Real pr = lane_xor<CTRL>(vr[0][r]), pi = lane_xor<CTRL>(vi[0][r]);
         const Real xr = vr[0][r], xi = vi[0][r];
-        vr[0][r] = fma(sr, xr, fma(-si, xi, fma(orr, pr, -oi * pi)));
-        vi[0][r] = fma(sr, xi, fma(si, xr, fma(orr, pi, oi * pr)));
+        if constexpr (REALM) {
+            vr[0][r] = fma(sr, xr, orr * pr);
+            vi[0][r] = fma(sr, xi, orr * pi);
+        } else {
+            vr[0][r] = fma(sr, xr, fma(-si, xi, fma(orr, pr, -oi * pi)));
+            vi[0][r] = fma(sr, xi, fma(si, xr, fma(orr, pi, oi * pr)));
+        }
     }
 }
 
@@ -386,7 +404,7 @@ __global__ void __launch_bounds__(256) k_tables(const TableJobs jobs, double2* _
 // layout walks); KC == 0: generic kernel with a runtime layout count (used for
 // states smaller than one tile and for real-valued instances).
 template <typename Real, int T, int R, int NV, int NS, int MINB, bool PH, bool INTE, int KC, int NTM = 0,
-          bool PERSIST = false, bool SPZ = PH, bool GEN = false>
+          bool PERSIST = false, bool SPZ = PH, int GEN = 0>
 __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
     using V2 = typename V2T<Real>::type;
     constexpr int NT = 1 << (T - R);
@@ -552,15 +570,16 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                         thr_goff = tg.gmap(thr_u);
                     }
                     const int act = fwd ? L->act_fwd : L->act_bwd;
-                    if constexpr (GEN) {
+                    if constexpr (GEN != 0) {
                         // general single-qubit layers (one vector, no pending scale)
                         static_assert(NV == 1, "general layers are one-vector passes");
                         const double* __restrict__ M = a.gmat + op.qidx * kGenBlock;
-                        gen_round<Real, R>(vr, vi, act, L->rbpack, M);
+                        constexpr bool RM = GEN == 2;
+                        gen_round<Real, R, RM>(vr, vi, act, L->rbpack, M);
                         const int dl = L->dpp;
-                        if (dl & 8) gen_lane<kLaneX8, 3, Real, R>(vr, vi, tmask_bit(L->tmask, 3), M);
+                        if (dl & 8) gen_lane<kLaneX8, 3, Real, R, RM>(vr, vi, tmask_bit(L->tmask, 3), M);
                         if constexpr (sizeof(Real) == 4 && T == 14) {
-                            if (dl & 16) gen_lane<kLaneX16, 4, Real, R>(vr, vi, tmask_bit(L->tmask, 4), M);
+                            if (dl & 16) gen_lane<kLaneX16, 4, Real, R, RM>(vr, vi, tmask_bit(L->tmask, 4), M);
                         }
                         return;
                     }
@@ -981,22 +1000,30 @@ static int run_pass(const PassArgs& a, void* stream) {
     hipStream_t st = (hipStream_t)stream;
     const bool fast = a.phantom == 0 && (a.lut_half >= 0 || a.nphase == 0);
     if constexpr (NV == 1 && (sizeof(Real) == 8 || T == 14)) {
-        if (a.gmat) {  // general single-qubit layers
+        if (a.gmat) {  // general single-qubit layers (real matrices: half the arithmetic)
             if (fast && !a.spin_part) {
-                if (a.nlayouts == 1)
-                    hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MINB, false, true, 1, 0, false, false, true>), grid,
-                                       block, 0, st, a);
-                else if (a.nlayouts == 2)
-                    hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MINB, false, true, 2, 0, false, false, true>), grid,
-                                       block, 0, st, a);
-                else if constexpr (sizeof(Real) == 8)  // three or more layouts exceed 256 registers:
-                    hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, 1, false, true, 0, 0, false, false, true>), grid,
-                                       block, 0, st, a);  // one workgroup per CU
-                else
-                    hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MINB, false, true, 0, 0, false, false, true>), grid,
-                                       block, 0, st, a);
+                const bool rm = a.gen_real != 0;
+                if (a.nlayouts == 1) {
+                    if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MINB, false, true, 1, 0, false, false, 2>),
+                                               grid, block, 0, st, a);
+                    else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MINB, false, true, 1, 0, false, false, 1>),
+                                            grid, block, 0, st, a);
+                } else if (a.nlayouts == 2) {
+                    if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MINB, false, true, 2, 0, false, false, 2>),
+                                               grid, block, 0, st, a);
+                    else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MINB, false, true, 2, 0, false, false, 1>),
+                                            grid, block, 0, st, a);
+                } else {
+                    // three or more layouts: complex matrices on complex128 amplitudes need
+                    // the whole register file (one workgroup per CU)
+                    constexpr int MB = sizeof(Real) == 8 ? 1 : MINB;
+                    if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MINB, false, true, 0, 0, false, false, 2>),
+                                               grid, block, 0, st, a);
+                    else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MB, false, true, 0, 0, false, false, 1>),
+                                            grid, block, 0, st, a);
+                }
             } else {
-                hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, 1, true, false, 0, 0, false, true, true>), grid, block,
+                hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, 1, true, false, 0, 0, false, true, 1>), grid, block,
                                    0, st, a);
             }
             return (int)hipGetLastError();

@@ -90,6 +90,48 @@ def test_product_state_full_size(sv, orc, dtype, n):
 
 
 @pytest.mark.parametrize("dtype,n", [("c128", 33), ("c64", 34)])
+def test_hadamard_circuit_full_size(sv, dtype, n):
+    """(H^{xN})^{11} on |+>^n gives |0...0> (the Hadamard benchmark circuit)."""
+    import torch
+
+    need_free((1 << n) * (16 if dtype == "c128" else 8))
+    had = np.array([[1, 1], [1, -1]], dtype=np.complex128) / np.sqrt(2.0)
+    s = sv.State(n, dtype)
+    sv.init_plus(s)
+    sv.gate_layers(s, np.broadcast_to(had, (11, n, 2, 2)))
+    zs = sample_indices(n, 4096, 60 + n)
+    got = s.tensor[torch.from_numpy(zs.astype(np.int64)).to(s.tensor.device)].cpu().numpy()
+    tol = 1e-11 if dtype == "c128" else 2e-5
+    assert abs(got[0] - 1.0) <= tol
+    assert np.max(np.abs(got[1:])) <= tol * 2.0 ** (-(n - 20) / 2)
+    assert abs(torch.linalg.vector_norm(s.tensor).item() - 1.0) <= tol
+    del s
+
+
+@pytest.mark.parametrize("dtype,n", [("c128", 33), ("c64", 34)])
+def test_qsds_product_state_full_size(sv, orc, dtype, n):
+    """Eq. AQA4 stepping of a J = 0 instance against the factorised oracle state."""
+    import torch
+
+    need_free((1 << n) * (16 if dtype == "c128" else 8))
+    inst = I.fields_only(n, 70 + n)
+    H = sv.Ising.from_instance(inst)
+    A, B = np.array([0.9, 0.6, 0.35, 0.1]), np.array([0.1, 0.4, 0.65, 0.9])
+    s = sv.State(n, dtype)
+    en, pg, sz = sv.qsds_run(s, H, 0.55, A, B, observe=True)
+    phi = orc.qsds_product_factors(inst["h"], 0.55, A, B)
+    zs = sample_indices(n, 4096, 71 + n)
+    got = s.tensor[torch.from_numpy(zs.astype(np.int64)).to(s.tensor.device)].cpu().numpy()
+    ref = orc.factor_amplitudes(phi, zs)
+    assert np.max(np.abs(got - ref)) <= AMP_TOL[dtype] * 2.0 ** (-(n - 20) / 2)
+    eref = orc.factor_energy(inst["h"], phi)
+    assert abs(en[-1] - eref) <= energy_tol(orc, inst, eref)
+    szref = np.abs(phi[:, 1]) ** 2 - np.abs(phi[:, 0]) ** 2
+    assert np.max(np.abs(sz[-1] - szref)) <= 10 * PROB_TOL[dtype]
+    del s
+
+
+@pytest.mark.parametrize("dtype,n", [("c128", 33), ("c64", 34)])
 def test_aqa_equals_qaoa_full_size(sv, dtype, n):
     need_free((1 << n) * (16 if dtype == "c128" else 8))
     inst = I.config4_instance(n)

@@ -481,3 +481,16 @@ def test_qsds_observables_per_step(orc):
     assert abs(en[1] - e2) < 1e-12 and abs(pg[1] - p2) < 1e-14
     assert np.max(np.abs(sz[-1] - orc.spin_z(7, psi))) < 1e-14
     assert np.array_equal(psi, orc.qsds_run(inst, 0.4, A, B))
+
+
+def test_qsds_product_factors_vs_full_state(orc):
+    """J = 0: the Eq. AQA4 state is the tensor product of the single-qubit factors."""
+    n = 7
+    inst = I.fields_only(n, 15)
+    A, B = np.array([0.9, 0.5, 0.2]), np.array([0.1, 0.6, 0.8])
+    psi = orc.qsds_run(inst, 0.7, A, B)
+    phi = orc.qsds_product_factors(inst["h"], 0.7, A, B)
+    zs = np.arange(1 << n, dtype=np.uint64)
+    assert np.max(np.abs(orc.factor_amplitudes(phi, zs) - psi)) < 1e-14
+    _, e, _ = orc.observables(inst, psi)
+    assert abs(orc.factor_energy(inst["h"], phi) - e) < 1e-13
