@@ -43,6 +43,8 @@ def main():
     ap.add_argument("--p", type=int, default=4)
     ap.add_argument("--dtype", default="c128")
     ap.add_argument("--no-extras", action="store_true", help="skip gradient / c64 / CPU-baseline legs")
+    ap.add_argument("--extras", default="all",
+                    help="comma list of extra legs: grad,c64,exact_cover,hadamard,qsds,optimizer,cpu (default all)")
     ap.add_argument("--cpu-sample-n", type=int, default=28)
     ap.add_argument("--cpu-sample-p", type=int, default=8)
     ap.add_argument("--knob", action="append", default=[], metavar="NAME=VALUE",
@@ -116,7 +118,10 @@ def main():
             "algorithmic_bytes_per_launch": avg_bytes}
 
     extras = {}
-    if not args.no_extras:
+    legs = set() if args.no_extras else (
+        {"grad", "c64", "exact_cover", "hadamard", "qsds", "optimizer", "cpu"} if args.extras == "all"
+        else set(args.extras.split(",")))
+    if "grad" in legs:
         # adjoint gradient vs finite differences (2p + 1 forward evaluations)
         lam = sv.State(n, args.dtype)
         sv.grad(s, lam, H, gam, bet)
@@ -133,6 +138,7 @@ def main():
                           "max_abs_grad": float(max(np.max(np.abs(dg)), np.max(np.abs(db))))}
         log(f"[bench] grad {t_grad:.2f} ms vs FD {t_fd:.2f} ms")
         del lam
+    if "c64" in legs:
         # complex64 storage, same instance
         s64 = sv.State(n, "c64")
         sv.qaoa_energy(s64, H, gam, bet)
@@ -146,6 +152,7 @@ def main():
                          "energy_diff_vs_c128": abs(o64[0] - out[0])}
         log(f"[bench] c64 {ms64:.3f} ms/step")
         del s64
+    if "exact_cover" in legs:
         # dense exact-cover-structured instance (F = 472 columns, half-integer
         # couplings between every pair of overlapping rows), rescaled angles
         a = I.exact_cover_matrix(n, 472, 4 + n)
@@ -164,6 +171,7 @@ def main():
                                  "rescale_r": rx, "energy_plus_C": ox[0] * 1.0 + Cx, "p_gs": ox[1]}
         log(f"[bench] exact cover {msx:.3f} ms/step")
         del Hx
+    if "hadamard" in legs:
         # Hadamard benchmark circuit (H^{xN})^{11} (general single-qubit layers)
         had = np.array([[1, 1], [1, -1]], dtype=np.complex128) / np.sqrt(2.0)
         U = np.ascontiguousarray(np.broadcast_to(had, (11, n, 2, 2)))
@@ -185,7 +193,9 @@ def main():
                               "passes": ph["launches"] / (reps + 1),
                               "pass_GBps": ph["bytes"] / (ph["ms"] * 1e-3) / 1e9 if ph["ms"] > 0 else None}
         log(f"[bench] hadamard circuit {msh:.3f} ms")
+    if "qsds" in legs:
         # Eq. AQA4 time stepping, 10 steps of the annealing Hamiltonian, no per-step observables
+        reps = 3
         st = 10
         sg = np.arange(st) / st
         sv.qsds_run(s, H, 0.5, 1.0 - sg, sg)
@@ -197,6 +207,7 @@ def main():
         msq = (time.perf_counter() - t0) * 1e3 / reps
         extras["qsds"] = {"steps": st, "ms_per_run": round(msq, 3), "ms_per_step": round(msq / st, 3)}
         log(f"[bench] qsds {msq:.3f} ms for {st} steps")
+    if "optimizer" in legs:
         # optimisation loop of the paper (SLSQP, 200-call cap) at n = 26, p = 4:
         # adjoint gradients against scipy's finite differences of energy calls
         from paper_2104_03293_amd import optimize as O
@@ -220,7 +231,7 @@ def main():
         del Ho
 
     cpu = None
-    if not args.no_extras:
+    if "cpu" in legs:
         cpu = cpu_baseline(args.cpu_sample_n, args.cpu_sample_p)
 
     res = {
