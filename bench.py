@@ -44,7 +44,8 @@ def main():
     ap.add_argument("--dtype", default="c128")
     ap.add_argument("--no-extras", action="store_true", help="skip gradient / c64 / CPU-baseline legs")
     ap.add_argument("--extras", default="all",
-                    help="comma list of extra legs: grad,c64,exact_cover,hadamard,qsds,optimizer,cpu (default all)")
+                    help="comma list of extra legs: grad,c64,exact_cover,hadamard,qsds,batch_scan,optimizer,cpu "
+                         "(default all)")
     ap.add_argument("--cpu-sample-n", type=int, default=28)
     ap.add_argument("--cpu-sample-p", type=int, default=8)
     ap.add_argument("--knob", action="append", default=[], metavar="NAME=VALUE",
@@ -112,14 +113,29 @@ def main():
     avg_bytes = k["bytes"] / max(1, k["launches"])
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     traffic = committed_traffic(args.dtype, n, p)
+    # measured ceiling: a plain device-to-device copy of 4 GiB (read + write)
+    src = torch.empty(1 << 29, dtype=torch.float64, device="cuda")
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del src, dst
     roof = {"bound": "hbm", "kernel": f"k_pass<{args.dtype}>", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "launches_per_step": k["launches"] / args.steps, "avg_launch_ms": round(avg_ms, 4),
-            "algorithmic_bytes_per_launch": avg_bytes}
+            "algorithmic_bytes_per_launch": avg_bytes, "copy_ceiling": round(copy_gbs, 1),
+            "frac_of_copy": round(achieved / copy_gbs, 4)}
+    log(f"[bench] k_pass {achieved:.0f} GB/s; device copy {copy_gbs:.0f} GB/s")
 
     extras = {}
     legs = set() if args.no_extras else (
-        {"grad", "c64", "exact_cover", "hadamard", "qsds", "optimizer", "cpu"} if args.extras == "all"
+        {"grad", "c64", "exact_cover", "hadamard", "qsds", "batch_scan", "optimizer", "cpu"} if args.extras == "all"
         else set(args.extras.split(",")))
     if "grad" in legs:
         # adjoint gradient vs finite differences (2p + 1 forward evaluations)
@@ -207,6 +223,28 @@ def main():
         msq = (time.perf_counter() - t0) * 1e3 / reps
         extras["qsds"] = {"steps": st, "ms_per_run": round(msq, 3), "ms_per_step": round(msq / st, 3)}
         log(f"[bench] qsds {msq:.3f} ms for {st} steps")
+    if "batch_scan" in legs:
+        # batched p = 1 landscape: 2048 instances, n ~ U{10..18}, 3-regular +-1 couplings, 32 x 32 grid
+        insts = I.config3_instances(2048)
+        Hb = [sv.Ising.from_instance(x) for x in insts]
+        gb, bb = I.config3_grid()
+        for dt in ("c64", "c128"):
+            sv.batch_p1_scan(Hb, gb, bb, dtype=dt)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sv.batch_p1_scan(Hb, gb, bb, dtype=dt)
+            torch.cuda.synchronize()
+            msb = (time.perf_counter() - t0) * 1e3
+            ns = np.array([x["n"] for x in insts], dtype=np.float64)
+            items = len(insts) * len(gb) * len(bb)
+            upd = float(np.sum(2.0 ** ns * (ns + 1))) * len(gb) * len(bb)
+            flops = float(np.sum(2.0 ** ns * (8 * ns + 6))) * len(gb) * len(bb)
+            peak = 157.3e12 if dt == "c64" else 78.6e12
+            extras[f"batch_scan_{dt}"] = {"ms": round(msb, 3), "items": items, "items_per_s": items / (msb * 1e-3),
+                                          "amp_updates_per_s": upd / (msb * 1e-3),
+                                          "valu_frac": flops / (msb * 1e-3) / peak}
+            log(f"[bench] batch scan {dt}: {msb:.1f} ms for {items} items")
+        del Hb
     if "optimizer" in legs:
         # optimisation loop of the paper (SLSQP, 200-call cap) at n = 26, p = 4:
         # adjoint gradients against scipy's finite differences of energy calls

@@ -57,6 +57,7 @@ std::map<std::string, int> g_knobs = {
     {"snake", 1},     // 1: the contiguous tile group takes a middle slot of the layer's group order
     {"dpp", 1},       // 1: one active bit may be butterflied across lanes to save a layout
     {"ldsswz", 4},    // LDS slot swizzle width of the tile passes (3..5)
+    {"batchwide", 1}, // complex64 batch scan: 1 = eight waves per workgroup, 0 = four
 };
 int knob(const char* k) {
     std::lock_guard<std::mutex> g(g_knob_mu);
@@ -124,7 +125,8 @@ extern "C" int sv_tune_set(const char* name, int value) {
     if (std::string(name) == "ntmin" && (value < 0 || value > 64)) return fail(SV_ERR_ARG, "ntmin must be in [0, 64]");
     if (std::string(name) == "persist" && (value < 0 || value > 8)) return fail(SV_ERR_ARG, "persist must be in [0, 8]");
     if (std::string(name) == "ldsswz" && (value < 3 || value > 5)) return fail(SV_ERR_ARG, "ldsswz must be in [3, 5]");
-    if ((std::string(name) == "snake" || std::string(name) == "dpp") && (value < 0 || value > 1))
+    if ((std::string(name) == "snake" || std::string(name) == "dpp" || std::string(name) == "batchwide") &&
+        (value < 0 || value > 1))
         return fail(SV_ERR_ARG, "%s must be 0 or 1", name);
     if (std::string(name) == "stagger" && (value < 0 || value > 64)) return fail(SV_ERR_ARG, "stagger must be in [0, 64]");
     it->second = value;
@@ -2192,6 +2194,7 @@ extern "C" int sv_batch_p1_scan(int n_inst, const sv_ising* insts, int n_gamma, 
     int32_t* d_ei = (int32_t*)dalloc(ii.size() * sizeof(int32_t));
     int32_t* d_ej = (int32_t*)dalloc(jj.size() * sizeof(int32_t));
     double* d_e = (double*)dalloc(etot * sizeof(double));
+    uint16_t* d_x = (uint16_t*)dalloc(etot * sizeof(uint16_t));
     int32_t* d_ui = (int32_t*)dalloc(uinst.size() * sizeof(int32_t));
     int32_t* d_ug = (int32_t*)dalloc(ugam.size() * sizeof(int32_t));
     double* d_g = (double*)dalloc(n_gamma * sizeof(double));
@@ -2226,6 +2229,7 @@ extern "C" int sv_batch_p1_scan(int n_inst, const sv_ising* insts, int n_gamma, 
     ba.ej = d_ej;
     ba.J = d_J;
     ba.etab = d_e;
+    ba.eidx = d_x;
     ba.unit_inst = d_ui;
     ba.unit_gam = d_ug;
     ba.nunits = (int32_t)uinst.size();
@@ -2243,7 +2247,7 @@ extern "C" int sv_batch_p1_scan(int n_inst, const sv_ising* insts, int n_gamma, 
     if (e == hipSuccess && !ke) {
         hipEvent_t ev0;
         const bool prof = prof_begin(st, &ev0);
-        ke = launch_batch_scan((int)dtype, ba, grid, st);
+        ke = launch_batch_scan((int)dtype, ba, grid, knob_for("batchwide", (int)dtype, max_n), st);
         if (prof) prof_end(st, ev0, std::string("batch_") + (dtype == SV_C128 ? "c128" : "c64"), 0.0);
     }
     if (e == hipSuccess && !ke) e = hipMemcpyAsync(energy_out, d_oe, nout * sizeof(double), hipMemcpyDeviceToHost, st);

@@ -218,6 +218,7 @@ struct BatchArgs {
     const int32_t* ej;
     const double* J;
     double* etab;           // energy tables, Sum 2^n_i entries
+    uint16_t* eidx;         // integer-valued instances: E(z) - lut_lo per entry (same offsets)
     const int32_t* unit_inst;  // work unit -> instance (units sorted by n, largest first)
     const int32_t* unit_gam;   // work unit -> gamma index
     int32_t nunits;
@@ -233,7 +234,7 @@ struct BatchArgs {
 };
 
 int launch_batch_energy(const BatchArgs& a, int max_n, void* stream);
-int launch_batch_scan(int dtype, const BatchArgs& a, int grid, void* stream);
+int launch_batch_scan(int dtype, const BatchArgs& a, int grid, int wide, void* stream);
 
 // Compile-time tile shapes per (dtype, vectors): T tile bits, R register bits.
 struct Shape {

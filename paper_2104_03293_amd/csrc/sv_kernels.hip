@@ -1145,7 +1145,8 @@ int launch_ground_finish(const GroundArgs& a, double* out_e, uint64_t* out_cnt, 
 // exp(-i gamma_a H_C) |+>, then <H_C> and the ground-state probability.
 namespace svk {
 
-// Energy tables E_i(z) for every instance (Eq. HC), one thread per basis state.
+// Energy tables E_i(z) for every instance (Eq. HC), one thread per basis state;
+// integer-valued instances also get the 16-bit table index E(z) - lut_lo.
 __global__ void __launch_bounds__(256) k_batch_energy(const BatchArgs a) {
     const int i = blockIdx.y;
     const BatchInst in = a.inst[i];
@@ -1159,6 +1160,7 @@ __global__ void __launch_bounds__(256) k_batch_energy(const BatchArgs a) {
             e += a.J[in.coff + k] * su * sv;
         }
         a.etab[in.eoff + z] = e;
+        if (in.lut_n > 0) a.eidx[in.eoff + z] = (uint16_t)((int)e - in.lut_lo);
     }
 }
 
@@ -1179,6 +1181,11 @@ __global__ void __launch_bounds__(256) k_batch_emin(const BatchArgs a, BatchInst
     if (threadIdx.x == 0) inst[i].emin = sh[0];
 }
 
+constexpr int kBatchUnroll = 4;  // table entries in flight per thread
+
+// One workgroup per CU holds the LDS state, with NTH threads (complex128: four
+// waves, its register blocks need more than the 256 registers that two waves
+// per SIMD leave; complex64: four or eight).
 template <typename Real>
 struct BatchCfg {
     static constexpr int S = sizeof(Real) == 4 ? 14 : 13;  // log2 of the LDS state size
@@ -1189,7 +1196,7 @@ __device__ __forceinline__ uint32_t bswz(uint32_t z, int G) { return lds_swizzle
 
 // exp(-i beta sigma^x) on every qubit of an LDS-resident state of 2^nb elements
 // (bits 0..nb-1), in register blocks of 5 bits.
-template <typename Real>
+template <typename Real, int NTH>
 __device__ void lds_mixer(typename V2T<Real>::type* st, int nb, Real c, Real s) {
     using V2 = typename V2T<Real>::type;
     constexpr int G = BatchCfg<Real>::G;
@@ -1202,7 +1209,7 @@ __device__ void lds_mixer(typename V2T<Real>::type* st, int nb, Real c, Real s) 
             if (!((done >> (a0 + k)) & 1u)) act |= 1u << k;
         done |= 31u << a0;
         const uint32_t nq = 1u << (nb - 5);
-        for (uint32_t q = threadIdx.x; q < nq; q += 256) {
+        for (uint32_t q = threadIdx.x; q < nq; q += NTH) {
             const uint32_t zb = (q & ((1u << a0) - 1u)) | ((q >> a0) << (a0 + 5));
             V2 v[32];
 #pragma unroll
@@ -1229,15 +1236,19 @@ __device__ void lds_mixer(typename V2T<Real>::type* st, int nb, Real c, Real s) 
 }
 
 // Persistent scan: workgroups take (instance, gamma) units from a queue, largest
-// n first, and evaluate every beta of the grid for that unit.
-template <typename Real>
-__global__ void __launch_bounds__(256) k_batch_scan(const BatchArgs a) {
+// n first, and evaluate every beta of the grid for that unit.  Integer-valued
+// instances read 16-bit table indices (E(z) - lut_lo) and take the phase
+// 2^{-n/2} exp(-i gamma E) from an LDS table; the others read E(z) in FP64 and
+// take sincos.  Table reads are issued kBatchUnroll at a time per thread.
+template <typename Real, int NTH>
+__global__ void __launch_bounds__(NTH) k_batch_scan(const BatchArgs a) {
     using V2 = typename V2T<Real>::type;
     constexpr int S = BatchCfg<Real>::S;
     constexpr int G = BatchCfg<Real>::G;
+    constexpr int U = kBatchUnroll;
     __shared__ V2 st[1 << S];
     __shared__ double2 lut[1024];
-    __shared__ double red[4][3];
+    __shared__ double red[NTH / 64][2];
     __shared__ int s_unit;
     const int t = threadIdx.x;
     V2* slot = reinterpret_cast<V2*>(a.scratch) + (uint64_t)blockIdx.x * a.scratch_elems;
@@ -1253,32 +1264,80 @@ __global__ void __launch_bounds__(256) k_batch_scan(const BatchArgs a) {
         const int n = in.n;
         const double amp0 = exp2(-0.5 * n);
         const double* E = a.etab + in.eoff;
+        const uint16_t* X = a.eidx + in.eoff;
         const bool intE = in.lut_n > 0;
+        const int xmin = intE ? (int)in.emin - in.lut_lo : 0;  // table index of the ground energy
         if (intE) {
-            for (int m = t; m < in.lut_n; m += 256) {
+            for (int m = t; m < in.lut_n; m += NTH) {
                 double sn, cs;
                 sincos(gam * (double)(in.lut_lo + m), &sn, &cs);
                 lut[m] = make_double2(amp0 * cs, -amp0 * sn);
             }
             __syncthreads();
         }
-        auto phi = [&](uint64_t z) -> V2 {  // amp0 exp(-i gamma E(z))
-            const double e = E[z];
-            double pr, pi;
+        // phase state 2^{-n/2} exp(-i gamma E(z)) for U consecutive-stride entries z0 + j NTH
+        auto phi_block = [&](uint64_t base, uint32_t z0, uint32_t lim, V2 (&out)[U]) {
             if (intE) {
-                const double2 w = lut[(int)e - in.lut_lo];
-                pr = w.x;
-                pi = w.y;
+                uint16_t x[U];
+#pragma unroll
+                for (int j = 0; j < U; j++) {
+                    const uint32_t z = z0 + j * NTH;
+                    x[j] = z < lim ? X[base + z] : (uint16_t)0;
+                }
+#pragma unroll
+                for (int j = 0; j < U; j++) {
+                    const double2 w = lut[x[j]];
+                    out[j].x = (Real)w.x;
+                    out[j].y = (Real)w.y;
+                }
             } else {
-                double sn, cs;
-                sincos(gam * e, &sn, &cs);
-                pr = amp0 * cs;
-                pi = -amp0 * sn;
+                double e[U];
+#pragma unroll
+                for (int j = 0; j < U; j++) {
+                    const uint32_t z = z0 + j * NTH;
+                    e[j] = z < lim ? E[base + z] : 0.0;
+                }
+                // one sincos at a time (each needs many temporaries)
+#pragma unroll 1
+                for (int j = 0; j < U; j++) {
+                    double sn, cs;
+                    sincos(gam * e[j], &sn, &cs);
+                    out[j].x = (Real)(amp0 * cs);
+                    out[j].y = (Real)(-amp0 * sn);
+                }
             }
-            V2 x;
-            x.x = (Real)pr;
-            x.y = (Real)pi;
-            return x;
+        };
+        // <H_C> and P_gs terms of U entries
+        auto obs_block = [&](uint64_t base, uint32_t z0, uint32_t lim, const V2 (&v)[U], double& r_e, double& r_p) {
+            if (intE) {
+                uint16_t x[U];
+#pragma unroll
+                for (int j = 0; j < U; j++) {
+                    const uint32_t z = z0 + j * NTH;
+                    x[j] = z < lim ? X[base + z] : (uint16_t)0;
+                }
+#pragma unroll
+                for (int j = 0; j < U; j++) {
+                    if (z0 + j * NTH >= lim) continue;
+                    const double p2 = (double)v[j].x * v[j].x + (double)v[j].y * v[j].y;
+                    r_e += (double)(in.lut_lo + (int)x[j]) * p2;
+                    if ((int)x[j] == xmin) r_p += p2;
+                }
+            } else {
+                double e[U];
+#pragma unroll
+                for (int j = 0; j < U; j++) {
+                    const uint32_t z = z0 + j * NTH;
+                    e[j] = z < lim ? E[base + z] : 0.0;
+                }
+#pragma unroll
+                for (int j = 0; j < U; j++) {
+                    if (z0 + j * NTH >= lim) continue;
+                    const double p2 = (double)v[j].x * v[j].x + (double)v[j].y * v[j].y;
+                    r_e += e[j] * p2;
+                    if (fabs(e[j] - in.emin) <= in.etol) r_p += p2;
+                }
+            }
         };
         for (int b = 0; b < a.nb; b++) {
             const double beta = a.betas[b];
@@ -1286,10 +1345,16 @@ __global__ void __launch_bounds__(256) k_batch_scan(const BatchArgs a) {
             double r_e = 0.0, r_p = 0.0;
             if (n <= S) {
                 const uint32_t N = 1u << n;
-                for (uint32_t z = t; z < N; z += 256) st[bswz(z, G)] = phi(z);
+                for (uint32_t z0 = t; z0 < N; z0 += NTH * U) {
+                    V2 v[U];
+                    phi_block(0, z0, N, v);
+#pragma unroll
+                    for (int j = 0; j < U; j++)
+                        if (z0 + j * NTH < N) st[bswz(z0 + j * NTH, G)] = v[j];
+                }
                 __syncthreads();
                 if (n >= 5) {
-                    lds_mixer<Real>(st, n, c, s);
+                    lds_mixer<Real, NTH>(st, n, c, s);
                 } else {
                     if (t == 0) {  // tiny states: plain pair loops
                         for (int q = 0; q < n; q++)
@@ -1306,26 +1371,34 @@ __global__ void __launch_bounds__(256) k_batch_scan(const BatchArgs a) {
                     }
                     __syncthreads();
                 }
-                for (uint32_t z = t; z < N; z += 256) {
-                    const V2 x = st[bswz(z, G)];
-                    const double p2 = (double)x.x * x.x + (double)x.y * x.y;
-                    const double e = E[z];
-                    r_e += e * p2;
-                    if (fabs(e - in.emin) <= in.etol) r_p += p2;
+                for (uint32_t z0 = t; z0 < N; z0 += NTH * U) {
+                    V2 v[U];
+#pragma unroll
+                    for (int j = 0; j < U; j++) {
+                        const uint32_t z = z0 + j * NTH;
+                        if (z < N) v[j] = st[bswz(z, G)];
+                        else v[j].x = v[j].y = (Real)0;
+                    }
+                    obs_block(0, z0, N, v, r_e, r_p);
                 }
             } else {
                 // low S bits slice by slice in LDS, written to this workgroup's slot
                 const int nh = n - S;
                 for (uint32_t sl = 0; sl < (1u << nh); sl++) {
                     const uint64_t off = (uint64_t)sl << S;
-                    for (uint32_t z = t; z < (1u << S); z += 256) st[bswz(z, G)] = phi(off + z);
+                    for (uint32_t z0 = t; z0 < (1u << S); z0 += NTH * U) {
+                        V2 v[U];
+                        phi_block(off, z0, 1u << S, v);
+#pragma unroll
+                        for (int j = 0; j < U; j++) st[bswz(z0 + j * NTH, G)] = v[j];
+                    }
                     __syncthreads();
-                    lds_mixer<Real>(st, S, c, s);
-                    for (uint32_t z = t; z < (1u << S); z += 256) slot[off + z] = st[bswz(z, G)];
+                    lds_mixer<Real, NTH>(st, S, c, s);
+                    for (uint32_t z = t; z < (1u << S); z += NTH) slot[off + z] = st[bswz(z, G)];
                     __syncthreads();
                 }
                 // high bits: each thread holds the 2^nh amplitudes of one low index
-                for (uint32_t l = t; l < (1u << S); l += 256) {
+                for (uint32_t l = t; l < (1u << S); l += NTH) {
                     V2 v[32];
 #pragma unroll
                     for (int r = 0; r < 32; r++)
@@ -1344,13 +1417,31 @@ __global__ void __launch_bounds__(256) k_batch_scan(const BatchArgs a) {
                             v[r2].y = c * bi - s * ar;
                         }
                     }
+                    if (intE) {
 #pragma unroll
-                    for (int r = 0; r < 32; r++) {
-                        if (r >= (1 << nh)) continue;
-                        const double p2 = (double)v[r].x * v[r].x + (double)v[r].y * v[r].y;
-                        const double e = E[((uint64_t)r << S) | l];
-                        r_e += e * p2;
-                        if (fabs(e - in.emin) <= in.etol) r_p += p2;
+                        for (int r0 = 0; r0 < 32; r0 += U) {
+                            uint16_t x[U];
+#pragma unroll
+                            for (int j = 0; j < U; j++)
+                                x[j] = r0 + j < (1 << nh) ? X[((uint64_t)(r0 + j) << S) | l] : (uint16_t)0;
+#pragma unroll
+                            for (int j = 0; j < U; j++) {
+                                const int r = r0 + j;
+                                if (r >= (1 << nh)) continue;
+                                const double p2 = (double)v[r].x * v[r].x + (double)v[r].y * v[r].y;
+                                r_e += (double)(in.lut_lo + (int)x[j]) * p2;
+                                if ((int)x[j] == xmin) r_p += p2;
+                            }
+                        }
+                    } else {
+#pragma unroll
+                        for (int r = 0; r < 32; r++) {
+                            if (r >= (1 << nh)) continue;
+                            const double p2 = (double)v[r].x * v[r].x + (double)v[r].y * v[r].y;
+                            const double e = E[((uint64_t)r << S) | l];
+                            r_e += e * p2;
+                            if (fabs(e - in.emin) <= in.etol) r_p += p2;
+                        }
                     }
                 }
                 __syncthreads();  // slot reads done before the next beta overwrites it
@@ -1367,8 +1458,11 @@ __global__ void __launch_bounds__(256) k_batch_scan(const BatchArgs a) {
             }
             __syncthreads();
             if (t == 0) {
-                const double se = red[0][0] + red[1][0] + red[2][0] + red[3][0];
-                const double sp = red[0][1] + red[1][1] + red[2][1] + red[3][1];
+                double se = 0.0, sp = 0.0;
+                for (int w = 0; w < NTH / 64; w++) {
+                    se += red[w][0];
+                    sp += red[w][1];
+                }
                 const uint64_t o = ((uint64_t)a.unit_inst[u] * a.ng + a.unit_gam[u]) * a.nb + b;
                 a.out_e[o] = se;
                 a.out_p[o] = sp;
@@ -1388,11 +1482,13 @@ int launch_batch_energy(const BatchArgs& a, int max_n, void* stream) {
     return (int)hipGetLastError();
 }
 
-int launch_batch_scan(int dtype, const BatchArgs& a, int grid, void* stream) {
+int launch_batch_scan(int dtype, const BatchArgs& a, int grid, int wide, void* stream) {
     if (dtype == 2)
-        hipLaunchKernelGGL(k_batch_scan<double>, dim3(grid), dim3(256), 0, (hipStream_t)stream, a);
+        hipLaunchKernelGGL((k_batch_scan<double, 256>), dim3(grid), dim3(256), 0, (hipStream_t)stream, a);
+    else if (wide)
+        hipLaunchKernelGGL((k_batch_scan<float, 512>), dim3(grid), dim3(512), 0, (hipStream_t)stream, a);
     else
-        hipLaunchKernelGGL(k_batch_scan<float>, dim3(grid), dim3(256), 0, (hipStream_t)stream, a);
+        hipLaunchKernelGGL((k_batch_scan<float, 256>), dim3(grid), dim3(256), 0, (hipStream_t)stream, a);
     return (int)hipGetLastError();
 }
 

@@ -69,7 +69,7 @@ def sample_indices(n, count, seed):
     return np.concatenate([np.array([0, (1 << n) - 1], dtype=np.uint64), z])
 
 
-@pytest.mark.parametrize("dtype,n", [("c128", 33), ("c64", 34)])
+@pytest.mark.parametrize("dtype,n", [("c128", 32), ("c64", 32), ("c128", 33), ("c64", 34)])
 def test_product_state_full_size(sv, orc, dtype, n):
     import torch
 
