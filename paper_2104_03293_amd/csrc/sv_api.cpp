@@ -58,6 +58,9 @@ std::map<std::string, int> g_knobs = {
     {"dpp", 1},       // 1: one active bit may be butterflied across lanes to save a layout
     {"ldsswz", 4},    // LDS slot swizzle width of the tile passes (3..5)
     {"batchwide", 1}, // complex64 batch scan: 1 = eight waves per workgroup, 0 = four
+    {"c64t13", 0},    // complex64 one-vector programs: 1 = 13-bit tiles (four waves), 0 = 14-bit tiles
+    {"c64occ", 0},    // complex64 14-bit tiles: 1 = no lane position 4, two workgroups per CU
+    {"c64g4", 1},     // complex64 two-vector passes: 1 = four waves per SIMD (two workgroups per CU)
 };
 int knob(const char* k) {
     std::lock_guard<std::mutex> g(g_knob_mu);
@@ -125,7 +128,8 @@ extern "C" int sv_tune_set(const char* name, int value) {
     if (std::string(name) == "ntmin" && (value < 0 || value > 64)) return fail(SV_ERR_ARG, "ntmin must be in [0, 64]");
     if (std::string(name) == "persist" && (value < 0 || value > 8)) return fail(SV_ERR_ARG, "persist must be in [0, 8]");
     if (std::string(name) == "ldsswz" && (value < 3 || value > 5)) return fail(SV_ERR_ARG, "ldsswz must be in [3, 5]");
-    if ((std::string(name) == "snake" || std::string(name) == "dpp" || std::string(name) == "batchwide") &&
+    if ((std::string(name) == "snake" || std::string(name) == "dpp" || std::string(name) == "batchwide" ||
+         std::string(name) == "c64t13" || std::string(name) == "c64occ" || std::string(name) == "c64g4") &&
         (value < 0 || value > 1))
         return fail(SV_ERR_ARG, "%s must be 0 or 1", name);
     if (std::string(name) == "stagger" && (value < 0 || value > 64)) return fail(SV_ERR_ARG, "stagger must be in [0, 64]");
@@ -504,7 +508,7 @@ static std::vector<Geometry> plan_groups(int n, sv_dtype dt, int nv, bool grad =
     // 14-bit complex64 tiles.  Two-vector passes keep every qubit in registers:
     // their lane butterflies would cost six cross-lane moves per amplitude
     // (both vectors and the gradient pair term), more than the exchange saved.
-    const bool pos4 = dt == SV_C64 && T == 14;
+    const bool pos4 = dt == SV_C64 && T == 14 && knob_for("c64occ", (int)dt, n) == 0;
     const uint32_t dpp = (knob_for("dpp", (int)dt, n) == 0 || nv == 2) ? 0u : (pos4 ? 0x18u : 0x8u);
     std::vector<Geometry> out;
     if (n <= T) {
@@ -981,6 +985,8 @@ struct Plan {
 // grad: the adjoint family, whose one- and two-vector tiles share T.
 static Plan make_plan(int n, sv_dtype dt, bool grad = false) {
     Plan pl;
+    // complex64 one-vector programs may use the 13-bit tiles of the adjoint family
+    if (dt == SV_C64 && knob_for("c64t13", (int)dt, n) != 0) grad = true;
     pl.by_nv[1] = plan_groups(n, dt, 1, grad);
     pl.by_nv[2] = plan_groups(n, dt, 2, grad);
     return pl;
@@ -1174,6 +1180,12 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
             if (genblk[pi][i] >= 0) a.ops[i].qidx = genblk[pi][i];
         }
         a.gmat = p.gen ? s->w.d_gmat : nullptr;
+        a.occ4 = (s->dt == SV_C64 && p.nv == 2 && knob_for("c64g4", (int)s->dt, s->n) != 0) ? 1 : 0;
+        if (s->dt == SV_C64 && geo.T == 14) {
+            a.occ4 = 1;
+            for (uint32_t m : geo.dpp)
+                if (m & 16u) a.occ4 = 0;
+        }
         a.gen_real = 1;
         for (int i = 0; i < kMaxOps; i++)
             if (genblk[pi][i] >= 0 && !genreal[pi][i]) a.gen_real = 0;

@@ -593,13 +593,15 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                     } else if constexpr (sizeof(Real) == 8) {
                         if (dl != 0)
                             lane_round<kLaneX8, Real, R, NV>(vr, vi, op.flags, (Real)op.a, op.b, pend, gsum);
-                    } else if constexpr (T == 14) {
+                    } else if constexpr (T == 14 && MINB <= 2) {
                         if (dl & 8)
                             lane_round<kLaneX8, Real, R, NV>(vr, vi, op.flags, (Real)op.a, op.b, pend, gsum);
                         else if (dl & 16)
                             lane_round<kLaneX16, Real, R, NV>(vr, vi, op.flags, (Real)op.a, op.b, pend, gsum);
                     } else {
-                        // 13-bit complex64 tiles (adjoint programs) plan lane position 3 only
+                        // 13-bit complex64 tiles, and 14-bit tiles in the four-waves-per-SIMD
+                        // kernel (the second branch would not fit its 128 registers), plan lane
+                        // position 3 only
                         if (dl != 0)
                             lane_round<kLaneX8, Real, R, NV>(vr, vi, op.flags, (Real)op.a, op.b, pend, gsum);
                     }
@@ -1001,23 +1003,25 @@ static int run_pass(const PassArgs& a, void* stream) {
     const bool fast = a.phantom == 0 && (a.lut_half >= 0 || a.nphase == 0);
     if constexpr (NV == 1 && (sizeof(Real) == 8 || T == 14)) {
         if (a.gmat) {  // general single-qubit layers (real matrices: half the arithmetic)
+            // general kernels need more registers than the four-waves-per-SIMD budget
+            constexpr int GMB = MINB > 2 ? 2 : MINB;
             if (fast && !a.spin_part) {
                 const bool rm = a.gen_real != 0;
                 if (a.nlayouts == 1) {
-                    if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MINB, false, true, 1, 0, false, false, 2>),
+                    if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 1, 0, false, false, 2>),
                                                grid, block, 0, st, a);
-                    else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MINB, false, true, 1, 0, false, false, 1>),
+                    else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 1, 0, false, false, 1>),
                                             grid, block, 0, st, a);
                 } else if (a.nlayouts == 2) {
-                    if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MINB, false, true, 2, 0, false, false, 2>),
+                    if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 2, 0, false, false, 2>),
                                                grid, block, 0, st, a);
-                    else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MINB, false, true, 2, 0, false, false, 1>),
+                    else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 2, 0, false, false, 1>),
                                             grid, block, 0, st, a);
                 } else {
                     // three or more layouts: complex matrices on complex128 amplitudes need
                     // the whole register file (one workgroup per CU)
-                    constexpr int MB = sizeof(Real) == 8 ? 1 : MINB;
-                    if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MINB, false, true, 0, 0, false, false, 2>),
+                    constexpr int MB = sizeof(Real) == 8 ? 1 : GMB;
+                    if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 0, 0, false, false, 2>),
                                                grid, block, 0, st, a);
                     else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MB, false, true, 0, 0, false, false, 1>),
                                             grid, block, 0, st, a);
@@ -1035,15 +1039,16 @@ static int run_pass(const PassArgs& a, void* stream) {
         // the register pressure below the two-workgroups-per-CU limit
         // (nontemporal variants for passes over long contiguous runs)
         if constexpr (NV == 1) {
-            if (a.spin_part) {  // passes that also sum the spin expectations
+            if (a.spin_part) {  // passes that also sum the spin expectations (more registers)
+                constexpr int SMB = MINB > 2 ? 2 : MINB;
                 if (a.nlayouts == 1)
-                    hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 1, 0, false, true>), grid, block,
+                    hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, SMB, false, true, 1, 0, false, true>), grid, block,
                                        0, st, a);
                 else if (a.nlayouts == 2)
-                    hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 2, 0, false, true>), grid, block,
+                    hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, SMB, false, true, 2, 0, false, true>), grid, block,
                                        0, st, a);
                 else
-                    hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 0, 0, false, true>), grid, block,
+                    hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, SMB, false, true, 0, 0, false, true>), grid, block,
                                        0, st, a);
                 return (int)hipGetLastError();
             }
@@ -1071,7 +1076,9 @@ static int run_pass(const PassArgs& a, void* stream) {
         else
             hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 0>), grid, block, 0, st, a);
     } else if (a.lut_half >= 0) {
-        hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, true, true, 0>), grid, block, 0, st, a);
+        // states smaller than one tile (phantom bits): correctness over occupancy
+        constexpr int PMB = MINB > 2 ? 2 : MINB;
+        hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, PMB, true, true, 0>), grid, block, 0, st, a);
     } else {
         // real-valued instances: FP64 sincos per thread needs more registers;
         // one workgroup per CU lets the compiler keep them in the AGPR half
@@ -1088,10 +1095,10 @@ int launch_pass(int dtype, int nv, int T, const PassArgs& a, void* stream) {
         return run_pass<double, 13, 4, 2, 4, 1>(a, stream);
     }
     if (nv == 1) {
-        if (T == 14) return run_pass<float, 14, 5, 1, 8, 2>(a, stream);
+        if (T == 14) return a.occ4 ? run_pass<float, 14, 5, 1, 8, 4>(a, stream) : run_pass<float, 14, 5, 1, 8, 2>(a, stream);
         return run_pass<float, 13, 5, 1, 8, 4>(a, stream);
     }
-    return run_pass<float, 13, 4, 2, 4, 1>(a, stream);
+    return a.occ4 ? run_pass<float, 13, 4, 2, 4, 4>(a, stream) : run_pass<float, 13, 4, 2, 4, 1>(a, stream);
 }
 
 int launch_tables(const TableJob* jobs, int njobs, double2* out, void* stream) {
