@@ -59,7 +59,7 @@ std::map<std::string, int> g_knobs = {
     {"ldsswz", 4},    // LDS slot swizzle width of the tile passes (3..5)
     {"batchwide", 1}, // complex64 batch scan: 1 = eight waves per workgroup, 0 = four
     {"c64t13", 0},    // complex64 one-vector programs: 1 = 13-bit tiles (four waves), 0 = 14-bit tiles
-    {"c64occ", 0},    // complex64 14-bit tiles: 1 = no lane position 4, two workgroups per CU
+    {"c64occ", 1},    // complex64 14-bit tiles: 1 = no lane position 4, two workgroups per CU
     {"c64g4", 1},     // complex64 two-vector passes: 1 = four waves per SIMD (two workgroups per CU)
 };
 int knob(const char* k) {

@@ -277,6 +277,29 @@ def test_lane_butterfly_plans(sv, orc, dtype, n):
     assert np.max(np.abs(s0.to_numpy() - s.to_numpy())) <= AMP_TOL[dtype]
 
 
+@pytest.mark.parametrize("n", [24])
+def test_complex64_lane_position_4_plans(sv, orc, n):
+    """complex64 14-bit tiles planned with lane position 4 allowed (knob c64occ=0:
+    the one-workgroup-per-CU kernel with both lane butterflies) against the
+    oracle and against the default plan."""
+    inst = instance_for(n, "int", 95 + n)
+    H = sv.Ising.from_instance(inst)
+    g, b = I.uniform_params(2, 96 + n, -1.0, 1.0)
+    ref = orc.qaoa_state(inst, g, b)
+    s1 = sv.State(n, "c64")
+    sv.qaoa_forward(s1, H, g, b)
+    sv.tune_set("c64occ", 0)
+    try:
+        used = [blk["dpp"] for grp in sv.describe(n, "c64")["plans"]["nv1"] for blk in grp["blocks"]]
+        s0 = sv.State(n, "c64")
+        sv.qaoa_forward(s0, H, g, b)
+    finally:
+        sv.tune_set("c64occ", 1)
+    assert any(d & 16 for d in used), used
+    assert np.max(np.abs(s0.to_numpy() - ref)) <= AMP_TOL["c64"]
+    assert np.max(np.abs(s1.to_numpy() - ref)) <= AMP_TOL["c64"]
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_zero_angles_identity(sv, dtype):
     n = 17
