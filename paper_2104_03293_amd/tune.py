@@ -11,6 +11,9 @@ Knobs swept:
                      runs of 2^c amplitudes; larger runs stream better but give
                      smaller groups, i.e. possibly more passes per layer)
   fuse             : snake-fused passes (1) or one mixer per pass (0)
+  snake            : the contiguous group in the middle of each layer's order (1) or first (0)
+  c64occ / c64t13  : complex64 only: 14-bit tiles without lane position 4 (two
+                     workgroups per CU) or with it; 13-bit tiles (four groups)
 Timing uses the library's per-launch HIP events (sv.profile_*) plus wall time.
 """
 from __future__ import annotations
@@ -25,8 +28,12 @@ from pathlib import Path
 def candidates(dtype: str):
     key = "cmin128" if dtype == "c128" else "cmin64"
     base = 3 if dtype == "c128" else 4
-    for c, f in itertools.product([base, base + 1, base + 2], [1, 0]):
-        yield {key: c, "fuse": f}
+    for c, f, sn in itertools.product([base, base + 1, base + 2], [1, 0], [1, 0]):
+        if dtype == "c128":
+            yield {key: c, "fuse": f, "snake": sn}
+        else:
+            for occ, t13 in ((1, 0), (0, 0), (1, 1)):
+                yield {key: c, "fuse": f, "snake": sn, "c64occ": occ, "c64t13": t13}
 
 
 def time_plan(sv, H, n, dtype, gam, bet, reps):
@@ -65,7 +72,7 @@ def main(argv=None):
 
     torch.cuda.set_device(0)
     sv.tune_load(None)  # tune against the built-in defaults
-    defaults = {k: sv.tune_get(k) for k in ("fuse", "cmin128", "cmin64")}
+    defaults = {k: sv.tune_get(k) for k in ("fuse", "cmin128", "cmin64", "snake", "c64occ", "c64t13")}
     lines = []
     for dtype in args.dtype:
         for n in args.n:
