@@ -57,7 +57,8 @@ std::map<std::string, int> g_knobs = {
     {"snake", 1},     // 1: the contiguous tile group takes a middle slot of the layer's group order
     {"dpp", 1},       // 1: one active bit may be butterflied across lanes to save a layout
     {"ldsswz", 4},    // LDS slot swizzle width of the tile passes (3..5)
-    {"batchwide", 1}, // complex64 batch scan: 1 = eight waves per workgroup, 0 = four
+    {"batchwide", 1}, // complex64 batch scan: 1 = 2^14 LDS states, eight waves; 0 = four waves;
+                      // 2 = 2^13 LDS states, four waves, two workgroups per CU
     {"c64t13", 0},    // complex64 one-vector programs: 1 = 13-bit tiles (four waves), 0 = 14-bit tiles
     {"c64occ", 1},    // complex64 14-bit tiles: 1 = no lane position 4, two workgroups per CU
     {"c64g4", 1},     // complex64 two-vector passes: 1 = four waves per SIMD (two workgroups per CU)
@@ -128,10 +129,12 @@ extern "C" int sv_tune_set(const char* name, int value) {
     if (std::string(name) == "ntmin" && (value < 0 || value > 64)) return fail(SV_ERR_ARG, "ntmin must be in [0, 64]");
     if (std::string(name) == "persist" && (value < 0 || value > 8)) return fail(SV_ERR_ARG, "persist must be in [0, 8]");
     if (std::string(name) == "ldsswz" && (value < 3 || value > 5)) return fail(SV_ERR_ARG, "ldsswz must be in [3, 5]");
-    if ((std::string(name) == "snake" || std::string(name) == "dpp" || std::string(name) == "batchwide" ||
-         std::string(name) == "c64t13" || std::string(name) == "c64occ" || std::string(name) == "c64g4") &&
+    if ((std::string(name) == "snake" || std::string(name) == "dpp" || std::string(name) == "c64t13" ||
+         std::string(name) == "c64occ" || std::string(name) == "c64g4") &&
         (value < 0 || value > 1))
         return fail(SV_ERR_ARG, "%s must be 0 or 1", name);
+    if (std::string(name) == "batchwide" && (value < 0 || value > 2))
+        return fail(SV_ERR_ARG, "batchwide must be in [0, 2]");
     if (std::string(name) == "stagger" && (value < 0 || value > 64)) return fail(SV_ERR_ARG, "stagger must be in [0, 64]");
     it->second = value;
     return SV_OK;
@@ -2131,7 +2134,10 @@ extern "C" int sv_batch_p1_scan(int n_inst, const sv_ising* insts, int n_gamma, 
         if (!std::isfinite(gammas[a])) return fail(SV_ERR_NUMERIC, "sv_batch_p1_scan: gamma %d not finite", a);
     for (int b = 0; b < n_beta; b++)
         if (!std::isfinite(betas[b])) return fail(SV_ERR_NUMERIC, "sv_batch_p1_scan: beta %d not finite", b);
-    const int nmax_batch = dtype == SV_C64 ? 19 : 18;
+    const int wide = dtype == SV_C64 ? knob_for("batchwide", (int)dtype, 0) : 0;
+    const int lut_cap = batch_lut_cap((int)dtype, wide);
+    const int S = batch_lds_bits((int)dtype, wide);
+    const int nmax_batch = S + 5;  // the high bits of a state fit one thread's 32 registers
     std::vector<BatchInst> bi(n_inst);
     std::vector<double> hh, JJ;
     std::vector<int32_t> ii, jj;
@@ -2157,7 +2163,7 @@ extern "C" int sv_batch_p1_scan(int n_inst, const sv_ising* insts, int n_gamma, 
         b.emin = 0.0;  // filled on the device
         b.etol = ground_tol(H);
         const int L = (int)std::ceil(H->scale);
-        if (H->integer && 2 * L + 1 <= 1024) {
+        if (H->integer && 2 * L + 1 <= lut_cap) {
             b.lut_lo = -L;
             b.lut_n = 2 * L + 1;
         } else {
@@ -2175,11 +2181,10 @@ extern "C" int sv_batch_p1_scan(int n_inst, const sv_ising* insts, int n_gamma, 
             uinst.push_back(i);
             ugam.push_back(a);
         }
-    const int S = dtype == SV_C64 ? 14 : 13;
     const size_t elem = elem_size(dtype);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-    const int grid = device_cu_count(dev);
+    const int grid = device_cu_count(dev) * (wide == 2 ? 2 : 1);
     const uint64_t slot = max_n > S ? (1ull << max_n) : 0;
     const size_t nout = (size_t)n_inst * n_gamma * n_beta;
     hipStream_t st = (hipStream_t)stream;
@@ -2259,7 +2264,7 @@ extern "C" int sv_batch_p1_scan(int n_inst, const sv_ising* insts, int n_gamma, 
     if (e == hipSuccess && !ke) {
         hipEvent_t ev0;
         const bool prof = prof_begin(st, &ev0);
-        ke = launch_batch_scan((int)dtype, ba, grid, knob_for("batchwide", (int)dtype, max_n), st);
+        ke = launch_batch_scan((int)dtype, ba, grid, wide, st);
         if (prof) prof_end(st, ev0, std::string("batch_") + (dtype == SV_C128 ? "c128" : "c64"), 0.0);
     }
     if (e == hipSuccess && !ke) e = hipMemcpyAsync(energy_out, d_oe, nout * sizeof(double), hipMemcpyDeviceToHost, st);

@@ -237,6 +237,8 @@ struct BatchArgs {
 
 int launch_batch_energy(const BatchArgs& a, int max_n, void* stream);
 int launch_batch_scan(int dtype, const BatchArgs& a, int grid, int wide, void* stream);
+int batch_lds_bits(int dtype, int wide);  // log2 of the LDS-resident state of a batch variant
+int batch_lut_cap(int dtype, int wide);   // phase-table entries of a batch variant
 
 // Compile-time tile shapes per (dtype, vectors): T tile bits, R register bits.
 struct Shape {

@@ -1195,8 +1195,7 @@ constexpr int kBatchUnroll = 4;  // table entries in flight per thread
 // per SIMD leave; complex64: four or eight).
 template <typename Real>
 struct BatchCfg {
-    static constexpr int S = sizeof(Real) == 4 ? 14 : 13;  // log2 of the LDS state size
-    static constexpr int G = sizeof(Real) == 4 ? 4 : 3;    // swizzle width
+    static constexpr int G = sizeof(Real) == 4 ? 4 : 3;  // LDS swizzle width
 };
 
 __device__ __forceinline__ uint32_t bswz(uint32_t z, int G) { return lds_swizzle(z, G); }
@@ -1247,14 +1246,13 @@ __device__ void lds_mixer(typename V2T<Real>::type* st, int nb, Real c, Real s) 
 // instances read 16-bit table indices (E(z) - lut_lo) and take the phase
 // 2^{-n/2} exp(-i gamma E) from an LDS table; the others read E(z) in FP64 and
 // take sincos.  Table reads are issued kBatchUnroll at a time per thread.
-template <typename Real, int NTH>
-__global__ void __launch_bounds__(NTH) k_batch_scan(const BatchArgs a) {
+template <typename Real, int NTH, int S, int LUTN, int MINW = 1>
+__global__ void __launch_bounds__(NTH, MINW) k_batch_scan(const BatchArgs a) {
     using V2 = typename V2T<Real>::type;
-    constexpr int S = BatchCfg<Real>::S;
     constexpr int G = BatchCfg<Real>::G;
     constexpr int U = kBatchUnroll;
     __shared__ V2 st[1 << S];
-    __shared__ double2 lut[1024];
+    __shared__ double2 lut[LUTN];
     __shared__ double red[NTH / 64][2];
     __shared__ int s_unit;
     const int t = threadIdx.x;
@@ -1489,13 +1487,21 @@ int launch_batch_energy(const BatchArgs& a, int max_n, void* stream) {
     return (int)hipGetLastError();
 }
 
+// Variants: complex128 2^13-amplitude LDS states, four waves; complex64 2^14 states with eight
+// waves (wide = 1) or four (wide = 0), one workgroup per CU; complex64 2^13 states with four
+// waves and a 512-entry phase table (wide = 2), two workgroups per CU.
+int batch_lds_bits(int dtype, int wide) { return dtype == 2 ? 13 : (wide == 2 ? 13 : 14); }
+int batch_lut_cap(int dtype, int wide) { return (dtype != 2 && wide == 2) ? 512 : 1024; }
+
 int launch_batch_scan(int dtype, const BatchArgs& a, int grid, int wide, void* stream) {
     if (dtype == 2)
-        hipLaunchKernelGGL((k_batch_scan<double, 256>), dim3(grid), dim3(256), 0, (hipStream_t)stream, a);
-    else if (wide)
-        hipLaunchKernelGGL((k_batch_scan<float, 512>), dim3(grid), dim3(512), 0, (hipStream_t)stream, a);
+        hipLaunchKernelGGL((k_batch_scan<double, 256, 13, 1024>), dim3(grid), dim3(256), 0, (hipStream_t)stream, a);
+    else if (wide == 1)
+        hipLaunchKernelGGL((k_batch_scan<float, 512, 14, 1024>), dim3(grid), dim3(512), 0, (hipStream_t)stream, a);
+    else if (wide == 2)
+        hipLaunchKernelGGL((k_batch_scan<float, 256, 13, 512, 2>), dim3(grid), dim3(256), 0, (hipStream_t)stream, a);
     else
-        hipLaunchKernelGGL((k_batch_scan<float, 256>), dim3(grid), dim3(256), 0, (hipStream_t)stream, a);
+        hipLaunchKernelGGL((k_batch_scan<float, 256, 14, 1024>), dim3(grid), dim3(256), 0, (hipStream_t)stream, a);
     return (int)hipGetLastError();
 }
 

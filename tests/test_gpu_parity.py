@@ -522,6 +522,27 @@ def test_batch_scan_vs_oracle(sv, orc, dtype):
         assert np.max(np.abs(pg[i] - rpg)) <= PROB_TOL[dtype], (i, inst["n"])
 
 
+@pytest.mark.parametrize("wide", [0, 2])
+def test_batch_scan_variants(sv, orc, wide):
+    """The other complex64 batch kernels (four waves per workgroup with 2^14 LDS
+    states; two workgroups per CU with 2^13 LDS states) against the oracle."""
+    ns = [3, 9, 12, 13, 14, 15, 17, 18]
+    insts = [I.regular3_pm1(n, 520 + k) if n >= 4 else instance_for(n, "real", 520 + k) for k, n in enumerate(ns)]
+    insts.append(I.random_real(14, 25, 78))
+    gam, bet = I.config3_grid(4, 5)
+    Hs = [sv.Ising.from_instance(x) for x in insts]
+    sv.tune_set("batchwide", wide)
+    try:
+        en, pg = sv.batch_p1_scan(Hs, gam, bet, dtype="c64")
+    finally:
+        sv.tune_set("batchwide", 1)
+    for i, inst in enumerate(insts):
+        ren, rpg = _batch_oracle(orc, inst, gam, bet)
+        tol = 1e-6 * max(orc.coeff_scale(inst), 1.0)
+        assert np.max(np.abs(en[i] - ren)) <= tol, (i, inst["n"])
+        assert np.max(np.abs(pg[i] - rpg)) <= PROB_TOL["c64"], (i, inst["n"])
+
+
 def test_batch_scan_closed_form_full_grid(sv, orc):
     """32 x 32 grid of the batched workload on 64 instances: <H_C> at every point
     against the depth-one closed form (test_oracle_pins.p1_closed_form_energy)."""
