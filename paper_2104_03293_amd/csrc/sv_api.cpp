@@ -62,6 +62,7 @@ std::map<std::string, int> g_knobs = {
     {"c64t13", 0},    // complex64 one-vector programs: 1 = 13-bit tiles (four waves), 0 = 14-bit tiles
     {"c64occ", 1},    // complex64 14-bit tiles: 1 = no lane position 4, two workgroups per CU
     {"c64g4", 1},     // complex64 two-vector passes: 1 = four waves per SIMD (two workgroups per CU)
+    {"kc34", 1},      // two-vector passes with 3 or 4 layouts: 1 = straight-line kernels, 0 = layout loop
 };
 int knob(const char* k) {
     std::lock_guard<std::mutex> g(g_knob_mu);
@@ -130,7 +131,7 @@ extern "C" int sv_tune_set(const char* name, int value) {
     if (std::string(name) == "persist" && (value < 0 || value > 8)) return fail(SV_ERR_ARG, "persist must be in [0, 8]");
     if (std::string(name) == "ldsswz" && (value < 3 || value > 5)) return fail(SV_ERR_ARG, "ldsswz must be in [3, 5]");
     if ((std::string(name) == "snake" || std::string(name) == "dpp" || std::string(name) == "c64t13" ||
-         std::string(name) == "c64occ" || std::string(name) == "c64g4") &&
+         std::string(name) == "c64occ" || std::string(name) == "c64g4" || std::string(name) == "kc34") &&
         (value < 0 || value > 1))
         return fail(SV_ERR_ARG, "%s must be 0 or 1", name);
     if (std::string(name) == "batchwide" && (value < 0 || value > 2))
@@ -1183,6 +1184,7 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
             if (genblk[pi][i] >= 0) a.ops[i].qidx = genblk[pi][i];
         }
         a.gmat = p.gen ? s->w.d_gmat : nullptr;
+        a.kc34 = knob_for("kc34", (int)s->dt, s->n);
         a.occ4 = (s->dt == SV_C64 && p.nv == 2 && knob_for("c64g4", (int)s->dt, s->n) != 0) ? 1 : 0;
         if (s->dt == SV_C64 && geo.T == 14) {
             a.occ4 = 1;

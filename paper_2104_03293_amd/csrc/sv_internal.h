@@ -161,6 +161,7 @@ struct PassArgs {
     double* spin_part;      // [ntiles][kTF] spin partials (passes with PT_SPINZ)
     const double* gmat;     // general single-qubit layers (passes whose MIX ops carry MIX_GEN), else null
     int32_t gen_real;       // every general layer of the pass is real
+    int32_t kc34;           // two-vector passes with three or four layouts: straight-line kernels
     int32_t occ4;           // complex64 14-bit tiles planned without lane position 4: kernel with
                             // four waves per SIMD (two workgroups per CU)
     uint32_t qph_off[kMaxPhase];

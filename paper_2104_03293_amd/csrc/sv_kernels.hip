@@ -1065,6 +1065,24 @@ static int run_pass(const PassArgs& a, void* stream) {
                 return (int)hipGetLastError();
             }
         }
+        if constexpr (NV == 2) {
+            // two-vector passes (one workgroup per CU, the whole register file): three and
+            // four layouts as straight-line walks
+            if (a.kc34 && a.nlayouts == 3) {
+                if (a.nt == 3)
+                    hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 3, 3>), grid, block, 0, st, a);
+                else
+                    hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 3>), grid, block, 0, st, a);
+                return (int)hipGetLastError();
+            }
+            if (a.kc34 && a.nlayouts == 4) {
+                if (a.nt == 3)
+                    hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 4, 3>), grid, block, 0, st, a);
+                else
+                    hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 4>), grid, block, 0, st, a);
+                return (int)hipGetLastError();
+            }
+        }
         if (a.nlayouts == 1)
             hipLaunchKernelGGL((k_pass<Real, T, R, NV, NS, MINB, false, true, 1>), grid, block, 0, st, a);
         else if (a.nlayouts == 2 && a.nt == 3)

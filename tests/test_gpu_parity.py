@@ -243,7 +243,7 @@ def test_group_orders_agree(sv, orc, dtype):
     assert np.max(np.abs(g1[2] - g0[2])) <= GRAD_TOL[dtype] * scale
 
 
-@pytest.mark.parametrize("dtype,n", [("c128", 23), ("c64", 24), ("c64", 9), ("c64", 16)])
+@pytest.mark.parametrize("dtype,n", [("c128", 23), ("c64", 24), ("c64", 10), ("c64", 16)])
 def test_lane_butterfly_plans(sv, orc, dtype, n):
     """Plans that butterfly one qubit across lanes (instead of one more LDS
     layout) against the oracle, for the forward state, the fused energy and the
