@@ -131,6 +131,14 @@ def main():
             "launches_per_step": k["launches"] / args.steps, "avg_launch_ms": round(avg_ms, 4),
             "algorithmic_bytes_per_launch": avg_bytes, "copy_ceiling": round(copy_gbs, 1),
             "frac_of_copy": round(achieved / copy_gbs, 4)}
+    # fusion accounting: passes over the state per layer, the one-pass floor (read + write of
+    # the state once per layer at peak) against the measured layer time, and the sweeps per layer
+    # of a gate-by-gate scheme (n R_x + n R_z + m coupling gates)
+    state_bytes = (1 << n) * (16 if args.dtype == "c128" else 8)
+    t_layer = ms / p * 1e-3
+    roof["passes_per_layer"] = round(k["launches"] / args.steps / p, 3)
+    roof["one_pass_floor_frac"] = round(2 * state_bytes / (HBM_PEAK_GBS * 1e9) / t_layer, 4)
+    roof["gate_sweeps_per_layer"] = 2 * n + len(inst["J"])
     log(f"[bench] k_pass {achieved:.0f} GB/s; device copy {copy_gbs:.0f} GB/s")
 
     extras = {}
