@@ -1017,6 +1017,13 @@ static int run_pass(const PassArgs& a, void* stream) {
                                                grid, block, 0, st, a);
                     else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 2, 0, false, false, 1>),
                                             grid, block, 0, st, a);
+                } else if (a.kc34 && a.nlayouts == 3) {
+                    // three layouts as a straight-line walk
+                    constexpr int MB = sizeof(Real) == 8 ? 1 : GMB;
+                    if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 3, 0, false, false, 2>),
+                                               grid, block, 0, st, a);
+                    else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MB, false, true, 3, 0, false, false, 1>),
+                                            grid, block, 0, st, a);
                 } else {
                     // three or more layouts: complex matrices on complex128 amplitudes need
                     // the whole register file (one workgroup per CU)
