@@ -987,10 +987,11 @@ struct Plan {
 };
 
 // grad: the adjoint family, whose one- and two-vector tiles share T.
-static Plan make_plan(int n, sv_dtype dt, bool grad = false) {
+static Plan make_plan(int n, sv_dtype dt, bool grad = false, bool general = false) {
     Plan pl;
     // complex64 one-vector programs may use the 13-bit tiles of the adjoint family
-    if (dt == SV_C64 && knob_for("c64t13", (int)dt, n) != 0) grad = true;
+    // (not programs with general single-qubit layers, whose kernels exist for 14-bit tiles)
+    if (dt == SV_C64 && !general && knob_for("c64t13", (int)dt, n) != 0) grad = true;
     pl.by_nv[1] = plan_groups(n, dt, 1, grad);
     pl.by_nv[2] = plan_groups(n, dt, 2, grad);
     return pl;
@@ -1793,7 +1794,7 @@ extern "C" int sv_gate_layers(sv_state s, int nlayers, const double* U) {
         if (!std::isfinite(U[i]))
             return fail(SV_ERR_NUMERIC, "sv_gate_layers: non-finite entry in layer %d, qubit %d", (int)(i / 8 / s->n),
                         (int)(i / 8 % s->n));
-    Plan plan = make_plan(s->n, s->dt);
+    Plan plan = make_plan(s->n, s->dt, false, true);
     const std::vector<int> order = group_order((int)plan.by_nv[1].size(), (int)s->dt, s->n);
     const int ng = (int)order.size();
     // Gates on different qubits commute, so each tile group takes up to four
@@ -1887,7 +1888,7 @@ extern "C" int sv_qsds_run(sv_state s, sv_ising H, int steps, double tau, const 
     // layer list and events
     std::vector<double> layers;
     auto add_layer = [&](const double* src) { layers.insert(layers.end(), src, src + (size_t)n * 8); };
-    Plan plan = make_plan(n, s->dt);
+    Plan plan = make_plan(n, s->dt, false, true);
     const std::vector<int> order = group_order((int)plan.by_nv[1].size(), (int)s->dt, n);
     std::vector<Event> ev;
     if (from_plus) ev.push_back(Event{EV_INIT});
@@ -2097,7 +2098,8 @@ extern "C" int sv_tune_describe(int n, sv_dtype dtype, char* buf, size_t len) {
     js += "},\"plans\":{";
     for (int fam = 0; fam < 3; fam++) {
         const int nv = fam == 2 ? 2 : 1;
-        const bool grad = fam >= 1;
+        // the one-vector family is what make_plan gives the forward programs
+        const bool grad = fam >= 1 || (dtype == SV_C64 && knob_for("c64t13", (int)dtype, n) != 0);
         std::vector<Geometry> groups = plan_groups(n, dtype, nv, grad);
         const char* key = fam == 0 ? "nv1" : (fam == 1 ? "grad_nv1" : "grad_nv2");
         js += std::string(fam == 0 ? "" : ",") + "\"" + key + "\":[";

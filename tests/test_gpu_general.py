@@ -176,3 +176,35 @@ def test_qsds_errors(sv):
         sv.qsds_run(s, H, 0.5, [0.5, 0.1], [0.1])
     with pytest.raises(sv.SVError):
         sv.qsds_run(s, H, 0.5, [], [])
+
+
+def test_general_layers_ignore_the_13_bit_tile_knob(sv, orc):
+    """With complex64 one-vector programs on 13-bit tiles (knob c64t13), programs with
+    general layers keep the 14-bit tiles their kernels exist for; QAOA itself
+    runs on the 13-bit plan.  Both against the oracle."""
+    n = 18
+    inst = instance_for(n, "int", 370)
+    H = sv.Ising.from_instance(inst)
+    U = rand_unitaries((2, n), 371)
+    psi0 = rand_state(n, 372)
+    g, b = I.uniform_params(2, 373, -1.0, 1.0)
+    sv.tune_set("c64t13", 1)
+    try:
+        s = sv.State(n, "c64")
+        s.from_numpy(psi0)
+        sv.gate_layers(s, U)
+        got_layers = s.to_numpy()
+        s2 = sv.State(n, "c64")
+        sv.qsds_run(s2, H, 0.5, [0.9, 0.4], [0.2, 0.7])
+        got_qsds = s2.to_numpy()
+        s3 = sv.State(n, "c64")
+        e = sv.qaoa_energy(s3, H, g, b)
+        got_qaoa = s3.to_numpy()
+    finally:
+        sv.tune_set("c64t13", 0)
+    assert np.max(np.abs(got_layers - orc.gate_layers(n, psi0, U))) <= AMP_TOL["c64"]
+    assert np.max(np.abs(got_qsds - orc.qsds_run(inst, 0.5, [0.9, 0.4], [0.2, 0.7]))) <= AMP_TOL["c64"]
+    ref = orc.qaoa_state(inst, g, b)
+    assert np.max(np.abs(got_qaoa - ref)) <= AMP_TOL["c64"]
+    _, ren, _ = orc.observables(inst, ref)
+    assert abs(e[0] - ren) <= energy_tol(orc, inst, ren)
