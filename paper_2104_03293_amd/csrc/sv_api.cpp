@@ -51,7 +51,7 @@ std::map<std::string, int> g_knobs = {
     {"fuse", 1},      // 1: snake-ordered fused passes; 0: one op per pass
     {"cmin64", 4},    // minimum carrier bits (contiguous run 2^c amplitudes) for complex64
     {"cmin128", 3},   // ... for complex128
-    {"ntmin", 6},     // passes whose contiguous runs hold >= 2^ntmin amplitudes stream with nontemporal hints
+    {"ntmin", 4},     // passes whose contiguous runs hold >= 2^ntmin amplitudes stream with nontemporal hints
     {"persist", 0},   // tile passes: workgroups per CU of a persistent grid (0: one workgroup per tile)
     {"stagger", 0},   // persistent grids: start delay of the second half (units of 64*127 clocks)
     {"snake", 1},     // 1: the contiguous tile group takes a middle slot of the layer's group order
@@ -63,6 +63,7 @@ std::map<std::string, int> g_knobs = {
     {"c64occ", 1},    // complex64 14-bit tiles: 1 = no lane position 4, two workgroups per CU
     {"c64g4", 1},     // complex64 two-vector passes: 1 = four waves per SIMD (two workgroups per CU)
     {"kc34", 1},      // two-vector passes with 3 or 4 layouts: 1 = straight-line kernels, 0 = layout loop
+    {"ntinit", 1},    // write-only first passes: 1 = nontemporal stores
 };
 int knob(const char* k) {
     std::lock_guard<std::mutex> g(g_knob_mu);
@@ -131,7 +132,8 @@ extern "C" int sv_tune_set(const char* name, int value) {
     if (std::string(name) == "persist" && (value < 0 || value > 8)) return fail(SV_ERR_ARG, "persist must be in [0, 8]");
     if (std::string(name) == "ldsswz" && (value < 3 || value > 5)) return fail(SV_ERR_ARG, "ldsswz must be in [3, 5]");
     if ((std::string(name) == "snake" || std::string(name) == "dpp" || std::string(name) == "c64t13" ||
-         std::string(name) == "c64occ" || std::string(name) == "c64g4" || std::string(name) == "kc34") &&
+         std::string(name) == "c64occ" || std::string(name) == "c64g4" || std::string(name) == "kc34" ||
+         std::string(name) == "ntinit") &&
         (value < 0 || value > 1))
         return fail(SV_ERR_ARG, "%s must be 0 or 1", name);
     if (std::string(name) == "batchwide" && (value < 0 || value > 2))
@@ -1156,6 +1158,7 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         a.nops = 0;
         a.need_e = 0;
         a.nt = (geo.phantom == 0 && geo.c >= ntmin) ? 3 : 0;
+        if (geo.phantom == 0 && (p.load & 4) && knob_for("ntinit", (int)s->dt, s->n) != 0) a.nt = 3;
         a.swz = lds_swz_bits(s->dt, s->n);
         a.grid = persist * ncu;
         a.stagger = stagger;
