@@ -989,6 +989,36 @@ Shape shape_for(int dtype, int nv, bool grad) {
     return nv == 1 ? Shape{13, 5} : Shape{13, 4};
 }
 
+// Full-tile general-layer passes: layout count, real or complex matrices, nontemporal hints.
+template <typename Real, int T, int R, int NS, int GMB, int NTM>
+static void launch_gen_fast(const PassArgs& a, dim3 grid, dim3 block, hipStream_t st) {
+    const bool rm = a.gen_real != 0;
+    // three or more layouts with complex matrices on complex128 amplitudes need the whole
+    // register file (one workgroup per CU)
+    constexpr int MB = sizeof(Real) == 8 ? 1 : GMB;
+    if (a.nlayouts == 1) {
+        if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 1, NTM, false, false, 2>), grid, block,
+                                   0, st, a);
+        else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 1, NTM, false, false, 1>), grid, block, 0,
+                                st, a);
+    } else if (a.nlayouts == 2) {
+        if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 2, NTM, false, false, 2>), grid, block,
+                                   0, st, a);
+        else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 2, NTM, false, false, 1>), grid, block, 0,
+                                st, a);
+    } else if (a.kc34 && a.nlayouts == 3) {  // straight-line walk
+        if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 3, NTM, false, false, 2>), grid, block,
+                                   0, st, a);
+        else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MB, false, true, 3, NTM, false, false, 1>), grid, block, 0,
+                                st, a);
+    } else {
+        if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 0, NTM, false, false, 2>), grid, block,
+                                   0, st, a);
+        else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MB, false, true, 0, NTM, false, false, 1>), grid, block, 0,
+                                st, a);
+    }
+}
+
 // Slot counts: one-vector passes carry up to 8 reduction slots (fused AQA
 // steps); two-vector passes need at most 4 (3 for the turnaround reductions
 // + 1 gradient slot, or 3 gradient slots).
@@ -1006,33 +1036,10 @@ static int run_pass(const PassArgs& a, void* stream) {
             // general kernels need more registers than the four-waves-per-SIMD budget
             constexpr int GMB = MINB > 2 ? 2 : MINB;
             if (fast && !a.spin_part) {
-                const bool rm = a.gen_real != 0;
-                if (a.nlayouts == 1) {
-                    if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 1, 0, false, false, 2>),
-                                               grid, block, 0, st, a);
-                    else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 1, 0, false, false, 1>),
-                                            grid, block, 0, st, a);
-                } else if (a.nlayouts == 2) {
-                    if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 2, 0, false, false, 2>),
-                                               grid, block, 0, st, a);
-                    else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 2, 0, false, false, 1>),
-                                            grid, block, 0, st, a);
-                } else if (a.kc34 && a.nlayouts == 3) {
-                    // three layouts as a straight-line walk
-                    constexpr int MB = sizeof(Real) == 8 ? 1 : GMB;
-                    if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 3, 0, false, false, 2>),
-                                               grid, block, 0, st, a);
-                    else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MB, false, true, 3, 0, false, false, 1>),
-                                            grid, block, 0, st, a);
-                } else {
-                    // three or more layouts: complex matrices on complex128 amplitudes need
-                    // the whole register file (one workgroup per CU)
-                    constexpr int MB = sizeof(Real) == 8 ? 1 : GMB;
-                    if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 0, 0, false, false, 2>),
-                                               grid, block, 0, st, a);
-                    else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MB, false, true, 0, 0, false, false, 1>),
-                                            grid, block, 0, st, a);
-                }
+                if (a.nt == 3)
+                    launch_gen_fast<Real, T, R, NS, GMB, 3>(a, grid, block, st);
+                else
+                    launch_gen_fast<Real, T, R, NS, GMB, 0>(a, grid, block, st);
             } else {
                 hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, 1, true, false, 0, 0, false, true, 1>), grid, block,
                                    0, st, a);
