@@ -570,3 +570,48 @@ def test_batch_scan_errors(sv):
     with pytest.raises(sv.SVError) as e:
         sv.batch_p1_scan([H], [0.1], [0.2], dtype="c128")
     assert e.value.code == 4
+
+
+# ----------------------------------------------------------------------------- degenerate cases
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [1, 7, 15, 20])
+def test_zero_hamiltonian(sv, orc, dtype, n):
+    """h = 0 and no couplings: every basis state is a ground state (E = 0), the cost
+    phase is the identity, <H_C> = 0, P_gs = 1 and the gradient vanishes."""
+    inst = {"n": n, "h": np.zeros(n), "ei": np.zeros(0, np.int32), "ej": np.zeros(0, np.int32), "J": np.zeros(0)}
+    H = sv.Ising.from_instance(inst)
+    emin, deg, arg = sv.ground(H)
+    assert emin == 0.0 and deg == 2 ** n and arg == 0
+    g, b = I.uniform_params(3, 400 + n, -2.0, 2.0)
+    s = sv.State(n, dtype)
+    e, pgs, nrm = sv.qaoa_energy(s, H, g, b)
+    ref = orc.qaoa_state(inst, g, b)
+    assert np.max(np.abs(s.to_numpy() - ref)) <= AMP_TOL[dtype]
+    assert abs(e) <= 1e-12 and abs(pgs - 1.0) <= PROB_TOL[dtype] * 10 and abs(nrm - 1.0) <= PROB_TOL[dtype] * 10
+    psi, lam = sv.State(n, dtype), sv.State(n, dtype)
+    f, dg, db = sv.grad(psi, lam, H, g, b)
+    assert abs(f) <= 1e-12 and np.max(np.abs(dg)) <= 1e-12 and np.max(np.abs(db)) <= 1e-12
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("beta", [0.0, math.pi / 4, math.pi / 2, -3 * math.pi / 4, math.pi, 7.3, -11.0])
+def test_mixer_angle_reduction(sv, orc, dtype, beta):
+    """Mixer angles at and beyond the reduction boundaries (multiples of pi/4, pi and
+    large |beta|) on a random state spanning several tile groups."""
+    n = 23
+    psi0 = rand_state(n, 410)
+    s = sv.State(n, dtype)
+    s.from_numpy(psi0)
+    sv.mixer(s, beta)
+    assert np.max(np.abs(s.to_numpy() - orc.mixer(n, psi0, beta))) <= AMP_TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_identity_parameters_keep_plus_state(sv, dtype):
+    """gamma = beta = 0 leaves |+>^n unchanged (every pass runs, nothing rotates)."""
+    n = 22
+    inst = instance_for(n, "int", 420)
+    H = sv.Ising.from_instance(inst)
+    s = sv.State(n, dtype)
+    sv.qaoa_forward(s, H, [0.0, 0.0], [0.0, 0.0])
+    assert np.max(np.abs(s.to_numpy() - 2.0 ** (-n / 2))) <= AMP_TOL[dtype] * 1e-2
