@@ -63,6 +63,7 @@ std::map<std::string, int> g_knobs = {
     {"c64occ", 1},    // complex64 14-bit tiles: 1 = no lane position 4, two workgroups per CU
     {"c64g4", 1},     // complex64 two-vector passes: 1 = four waves per SIMD (two workgroups per CU)
     {"kc34", 1},      // two-vector passes with 3 or 4 layouts: 1 = straight-line kernels, 0 = layout loop
+    {"c64g14", 2},    // complex64 adjoint programs on 14-bit tiles: 1 always, 2 when fewer groups, 0 never
     {"ntinit", 1},    // write-only first passes: 1 = nontemporal stores
 };
 int knob(const char* k) {
@@ -136,6 +137,7 @@ extern "C" int sv_tune_set(const char* name, int value) {
          std::string(name) == "ntinit") &&
         (value < 0 || value > 1))
         return fail(SV_ERR_ARG, "%s must be 0 or 1", name);
+    if (std::string(name) == "c64g14" && (value < 0 || value > 2)) return fail(SV_ERR_ARG, "c64g14 must be in [0, 2]");
     if (std::string(name) == "batchwide" && (value < 0 || value > 2))
         return fail(SV_ERR_ARG, "batchwide must be in [0, 2]");
     if (std::string(name) == "stagger" && (value < 0 || value > 64)) return fail(SV_ERR_ARG, "stagger must be in [0, 64]");
@@ -508,7 +510,16 @@ static Geometry make_geometry(int n, int T, int R, int c, int lo, int g, int G, 
 // then the bits above T split into near-equal groups of at most T - cmin bits,
 // each tile carrying 2^c contiguous amplitudes (c = T - g >= cmin).
 static std::vector<Geometry> plan_groups(int n, sv_dtype dt, int nv, bool grad = false) {
-    const Shape sh = shape_for((int)dt, nv, grad);
+    Shape sh = shape_for((int)dt, nv, grad);
+    // complex64 adjoint family on 14-bit tiles: the forward tiles, and 1024-thread two-vector
+    // tiles of 4 register bits.  Knob c64g14: 1 always, 2 (default) when that needs fewer tile
+    // groups than the 13-bit family (e.g. three instead of four at n = 32), 0 never.
+    if (dt == SV_C64 && grad) {
+        const int mode = knob_for("c64g14", (int)dt, n);
+        const int cm = std::max(swz_bits(dt), knob_for("cmin64", (int)dt, n));
+        auto ngroups = [&](int T) { return n <= T ? 1 : 1 + (n - T + (T - cm) - 1) / (T - cm); };
+        if (mode == 1 || (mode == 2 && ngroups(14) < ngroups(13))) sh = nv == 1 ? Shape{14, 5} : Shape{14, 4};
+    }
     const int T = sh.T, R = sh.R, G = swz_bits(dt);
     // lane positions the one-vector kernels butterfly across lanes: 3, and 4 for
     // 14-bit complex64 tiles.  Two-vector passes keep every qubit in registers:

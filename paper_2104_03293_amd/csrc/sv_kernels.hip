@@ -1130,6 +1130,7 @@ int launch_pass(int dtype, int nv, int T, const PassArgs& a, void* stream) {
         if (T == 14) return a.occ4 ? run_pass<float, 14, 5, 1, 8, 4>(a, stream) : run_pass<float, 14, 5, 1, 8, 2>(a, stream);
         return run_pass<float, 13, 5, 1, 8, 4>(a, stream);
     }
+    if (T == 14) return run_pass<float, 14, 4, 2, 4, 4>(a, stream);  // 1024 threads
     return a.occ4 ? run_pass<float, 13, 4, 2, 4, 4>(a, stream) : run_pass<float, 13, 4, 2, 4, 1>(a, stream);
 }
 

@@ -615,3 +615,25 @@ def test_identity_parameters_keep_plus_state(sv, dtype):
     s = sv.State(n, dtype)
     sv.qaoa_forward(s, H, [0.0, 0.0], [0.0, 0.0])
     assert np.max(np.abs(s.to_numpy() - 2.0 ** (-n / 2))) <= AMP_TOL[dtype] * 1e-2
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("n", [9, 15, 18, 21])
+def test_complex64_adjoint_tile_sizes(sv, orc, mode, n):
+    """The complex64 adjoint on 13-bit tiles (c64g14=0) and on 14-bit tiles with
+    1024-thread two-vector passes (c64g14=1), against the oracle gradient."""
+    p = 3
+    inst = instance_for(n, "int" if n % 2 else "real", 430 + n)
+    H = sv.Ising.from_instance(inst)
+    g, b = I.uniform_params(p, 431 + n, -1.0, 1.0)
+    sv.tune_set("c64g14", mode)
+    try:
+        psi, lam = sv.State(n, "c64"), sv.State(n, "c64")
+        e, pg, dg, db = sv.grad(psi, lam, H, g, b, with_pgs=True)
+    finally:
+        sv.tune_set("c64g14", 2)
+    f, rg, rb = orc.grad_tangent(inst, g, b)
+    scale = max(np.max(np.abs(np.concatenate([rg, rb]))), orc.coeff_scale(inst))
+    assert abs(e - f) <= energy_tol(orc, inst, f)
+    assert np.max(np.abs(dg - rg)) <= GRAD_TOL["c64"] * scale
+    assert np.max(np.abs(db - rb)) <= GRAD_TOL["c64"] * scale
