@@ -637,3 +637,26 @@ def test_complex64_adjoint_tile_sizes(sv, orc, mode, n):
     assert abs(e - f) <= energy_tol(orc, inst, f)
     assert np.max(np.abs(dg - rg)) <= GRAD_TOL["c64"] * scale
     assert np.max(np.abs(db - rb)) <= GRAD_TOL["c64"] * scale
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_autograd_function(sv, orc, dtype):
+    """QAOAEnergy (torch.autograd.Function over the adjoint sweep): the energy and the
+    gradients that reach gamma and beta through a downstream expression."""
+    import torch
+
+    n, p = 16, 3
+    inst = instance_for(n, "int", 440)
+    H = sv.Ising.from_instance(inst)
+    g0, b0 = I.uniform_params(p, 441, -1.0, 1.0)
+    g = torch.tensor(g0, dtype=torch.float64, requires_grad=True)
+    b = torch.tensor(b0, dtype=torch.float64, requires_grad=True)
+    psi, lam = sv.State(n, dtype), sv.State(n, dtype)
+    e = sv.QAOAEnergy.apply(g, b, psi, lam, H)
+    loss = 3.0 * e + e * e
+    loss.backward()
+    f, rg, rb = orc.grad_tangent(inst, g0, b0)
+    assert abs(e.item() - f) <= energy_tol(orc, inst, f)
+    scale = max(np.max(np.abs(np.concatenate([rg, rb]))), orc.coeff_scale(inst)) * abs(3.0 + 2.0 * f)
+    assert np.max(np.abs(g.grad.numpy() - (3.0 + 2.0 * f) * rg)) <= GRAD_TOL[dtype] * scale
+    assert np.max(np.abs(b.grad.numpy() - (3.0 + 2.0 * f) * rb)) <= GRAD_TOL[dtype] * scale
