@@ -54,7 +54,7 @@ def main():
                     help="run one plain device-to-device copy of this size first (counter reference)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1"}), flush=True)
         sys.exit(2)
 
     import numpy as np
@@ -77,7 +77,7 @@ def main():
         log(f"[bench] reference copy of {args.copy_ref_mib} MiB done")
         del src, dst
     n, p = args.n, args.p
-    inst = I.config4_instance(n) if n >= 33 else I.degree4_int2(n, 4 + n)
+    inst = I.full_size_instance(n) if n >= 33 else I.degree4_int2(n, 4 + n)
     H = sv.Ising.from_instance(inst)
     gam, bet = I.linear_ramp_params(p)
     log(f"[bench] n={n} p={p} dtype={args.dtype} ground...")
@@ -233,9 +233,9 @@ def main():
         log(f"[bench] qsds {msq:.3f} ms for {st} steps")
     if "batch_scan" in legs:
         # batched p = 1 landscape: 2048 instances, n ~ U{10..18}, 3-regular +-1 couplings, 32 x 32 grid
-        insts = I.config3_instances(2048)
+        insts = I.batch_instances(2048)
         Hb = [sv.Ising.from_instance(x) for x in insts]
-        gb, bb = I.config3_grid()
+        gb, bb = I.batch_grid()
         for dt in ("c64", "c128"):
             sv.batch_p1_scan(Hb, gb, bb, dtype=dt)
             torch.cuda.synchronize()
@@ -257,7 +257,7 @@ def main():
         # optimisation loop of the paper (SLSQP, 200-call cap) at n = 26, p = 4:
         # adjoint gradients against scipy's finite differences of energy calls
         from paper_2104_03293_amd import optimize as O
-        Ho = sv.Ising.from_instance(I.config1_instance(26))
+        Ho = sv.Ising.from_instance(I.aqa_degree4_instance(26))
         dev = O.DeviceQAOA(Ho, args.dtype)
         g0, b0 = O.second_order_init(p, 0.5)
         opt = {}

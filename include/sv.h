@@ -47,7 +47,7 @@ typedef enum {
     SV_ERR_ARG = 1,         /* bad argument (nothing was changed)              */
     SV_ERR_OOM = 2,         /* device or host allocation failed                 */
     SV_ERR_HIP = 3,         /* HIP runtime error (state marked failed)          */
-    SV_ERR_UNSUPPORTED = 4, /* valid request this build does not handle         */
+    SV_ERR_UNSUPPORTED = 4, /* valid request the library does not handle        */
     SV_ERR_NUMERIC = 5      /* non-finite angle or coefficient                  */
 } sv_status;
 

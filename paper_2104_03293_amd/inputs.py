@@ -140,26 +140,26 @@ def exact_cover_matrix(nrows: int, ncols: int, seed: int, nplanted: int | None =
     return a
 
 
-# --- the five workloads ----------------------------------------------------------
+# --- the benchmark workloads ----------------------------------------------------------
 
-def config0_instance() -> dict:
+def small_regular3_instance() -> dict:
     """n=14, 3-regular, J in {-1,+1}, h in {-1,0,1}, seed 0."""
     return regular3_pm1(14, 0)
 
 
-CONFIG0_GAMMA, CONFIG0_BETA = 0.4, 0.3
+SMALL_GAMMA, SMALL_BETA = 0.4, 0.3
 
 
-def config1_instance(n: int = 26) -> dict:
+def aqa_degree4_instance(n: int = 26) -> dict:
     """n=26, G(26,52), integer J in [-2,2], h in {-1,0,1}, seed 1."""
     return degree4_int2(n, 1)
 
 
-def config2_instance(n: int = 30) -> dict:
+def grad_degree4_instance(n: int = 30) -> dict:
     return degree4_int2(n, 2)
 
 
-def config3_instances(count: int = 2048, nmin: int = 10, nmax: int = 18, base_seed: int = 3000) -> list:
+def batch_instances(count: int = 2048, nmin: int = 10, nmax: int = 18, base_seed: int = 3000) -> list:
     """Batched scan: instance k has n ~ U{nmin..nmax} (drawn from seed base_seed+k)."""
     out = []
     for k in range(count):
@@ -169,14 +169,14 @@ def config3_instances(count: int = 2048, nmin: int = 10, nmax: int = 18, base_se
     return out
 
 
-def config3_grid(ng: int = 32, nb: int = 32):
+def batch_grid(ng: int = 32, nb: int = 32):
     """Half-open grid gamma_a = a*pi/ng, beta_b = (pi/2)*b/nb (a, b = 0..ng-1, nb-1)."""
     g = np.arange(ng) * (math.pi / ng)
     b = np.arange(nb) * (0.5 * math.pi / nb)
     return g, b
 
 
-def config4_instance(n: int) -> dict:
+def full_size_instance(n: int) -> dict:
     return degree4_int2(n, 4 + n)
 
 

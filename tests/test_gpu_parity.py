@@ -181,14 +181,14 @@ def test_qaoa_from_given_state(sv, orc, dtype, n):
     assert np.max(np.abs(s.to_numpy() - ref)) <= AMP_TOL[dtype]
 
 
-def test_config0(sv, orc):
+def test_small_regular3_p1(sv, orc):
     """n = 14, p = 1, gamma = 0.4, beta = 0.3, complex128, 3-regular +-1 instance."""
-    inst = I.config0_instance()
+    inst = I.small_regular3_instance()
     H = sv.Ising.from_instance(inst)
     s = sv.State(14, "c128")
-    sv.qaoa_forward(s, H, [I.CONFIG0_GAMMA], [I.CONFIG0_BETA])
+    sv.qaoa_forward(s, H, [I.SMALL_GAMMA], [I.SMALL_BETA])
     E = orc.energies(inst)
-    ref = orc.qaoa_state(inst, [I.CONFIG0_GAMMA], [I.CONFIG0_BETA], E=E)
+    ref = orc.qaoa_state(inst, [I.SMALL_GAMMA], [I.SMALL_BETA], E=E)
     assert np.max(np.abs(s.to_numpy() - ref)) <= 1e-11
     en, pgs, nrm = sv.expect(s, H)
     _, ren, rpgs = orc.observables(inst, ref, E=E)
@@ -512,7 +512,7 @@ def test_batch_scan_vs_oracle(sv, orc, dtype):
         else:
             insts.append(instance_for(n, "real", 500 + k))
     insts.append(I.random_real(11, 20, 77))
-    gam, bet = I.config3_grid(6, 5)
+    gam, bet = I.batch_grid(6, 5)
     Hs = [sv.Ising.from_instance(x) for x in insts]
     en, pg = sv.batch_p1_scan(Hs, gam, bet, dtype=dtype)
     for i, inst in enumerate(insts):
@@ -529,7 +529,7 @@ def test_batch_scan_variants(sv, orc, wide):
     ns = [3, 9, 12, 13, 14, 15, 17, 18]
     insts = [I.regular3_pm1(n, 520 + k) if n >= 4 else instance_for(n, "real", 520 + k) for k, n in enumerate(ns)]
     insts.append(I.random_real(14, 25, 78))
-    gam, bet = I.config3_grid(4, 5)
+    gam, bet = I.batch_grid(4, 5)
     Hs = [sv.Ising.from_instance(x) for x in insts]
     sv.tune_set("batchwide", wide)
     try:
@@ -548,8 +548,8 @@ def test_batch_scan_closed_form_full_grid(sv, orc):
     against the depth-one closed form (test_oracle_pins.p1_closed_form_energy)."""
     from tests.test_oracle_pins import p1_closed_form_energy
 
-    insts = I.config3_instances(64)
-    gam, bet = I.config3_grid()
+    insts = I.batch_instances(64)
+    gam, bet = I.batch_grid()
     Hs = [sv.Ising.from_instance(x) for x in insts]
     en, pg = sv.batch_p1_scan(Hs, gam, bet, dtype="c64")
     for i in range(0, 64, 7):

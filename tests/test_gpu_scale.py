@@ -134,7 +134,7 @@ def test_qsds_product_state_full_size(sv, orc, dtype, n):
 @pytest.mark.parametrize("dtype,n", [("c128", 33), ("c64", 34)])
 def test_aqa_equals_qaoa_full_size(sv, dtype, n):
     need_free((1 << n) * (16 if dtype == "c128" else 8))
-    inst = I.config4_instance(n)
+    inst = I.full_size_instance(n)
     H = sv.Ising.from_instance(inst)
     g, b = sv.schedule_linear(10, 0.5)
     s = sv.State(n, dtype, owner="lib")
@@ -153,7 +153,7 @@ def test_aqa_equals_qaoa_full_size(sv, dtype, n):
 def test_grad_full_size_c128_n33(sv, orc):
     n, p = 33, 4
     need_free(2 * (1 << n) * 16)
-    inst = I.config4_instance(n)
+    inst = I.full_size_instance(n)
     H = sv.Ising.from_instance(inst)
     g, b = I.linear_ramp_params(p)
     psi = sv.State(n, "c128", owner="lib")
@@ -183,12 +183,12 @@ def test_grad_full_size_c128_n33(sv, orc):
     psi.close()
 
 
-def test_grad_config2_c64_n30(sv, orc):
+def test_grad_c64_n30_p8(sv, orc):
     """n = 30, p = 8: complex64 adjoint (16 parameters) against the complex128
     adjoint and central differences of the complex128 energy."""
     n, p = 30, 8
     need_free(2 * (1 << n) * 16 + 2 * (1 << n) * 8)
-    inst = I.config2_instance(n)
+    inst = I.grad_degree4_instance(n)
     H = sv.Ising.from_instance(inst)
     g, b = I.linear_ramp_params(p)
     psi, lam = sv.State(n, "c64"), sv.State(n, "c64")
@@ -225,7 +225,7 @@ def test_grad_config2_c64_n30(sv, orc):
 def aqa26_reference(orc):
     """Oracle per-step (<H_C>, P_gs) of the n = 26 AQA run (20 steps, tau = 0.5)."""
     n = 26
-    inst = I.config1_instance(n)
+    inst = I.aqa_degree4_instance(n)
     g, b = orc.aqa_linear_schedule(20, 0.5)
     E = orc.energies(inst)
     gs = orc.ground(inst, E)
@@ -239,7 +239,7 @@ def aqa26_reference(orc):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_aqa_config1_n26(sv, orc, aqa26_reference, dtype):
+def test_aqa_n26_20_steps(sv, orc, aqa26_reference, dtype):
     """n = 26, 20 coarse steps, tau = 0.5, paper sign: per-step P_gs and <H_C>
     against the oracle; tau = 1.0 with the literal sign against the paper sign
     on the negated problem (<H>_literal(H) = -<H>_paper(-H) at every step)."""

@@ -53,7 +53,7 @@ def test_energy_parity_and_complement(orc):
 
 
 def test_ground_brute_force(orc):
-    for inst in small_instances() + [I.config0_instance()]:
+    for inst in small_instances() + [I.small_regular3_instance()]:
         E = orc.energies(inst)
         emin, deg, am = orc.ground(inst, E)
         assert emin == E.min()
@@ -213,11 +213,11 @@ def test_general_p1_closed_form(orc, seed):
             assert abs(en - p1_closed_form_energy(inst, g, b)) < 1e-12 * max(1, orc.coeff_scale(inst))
 
 
-def test_config0_energy_closed_form(orc):
-    inst = I.config0_instance()
-    psi = orc.qaoa_state(inst, [I.CONFIG0_GAMMA], [I.CONFIG0_BETA])
+def test_small_regular3_energy_closed_form(orc):
+    inst = I.small_regular3_instance()
+    psi = orc.qaoa_state(inst, [I.SMALL_GAMMA], [I.SMALL_BETA])
     en = orc.observables(inst, psi)[1]
-    assert abs(en - p1_closed_form_energy(inst, I.CONFIG0_GAMMA, I.CONFIG0_BETA)) < 1e-12
+    assert abs(en - p1_closed_form_energy(inst, I.SMALL_GAMMA, I.SMALL_BETA)) < 1e-12
 
 
 def test_grid_edges(orc):
