@@ -1,6 +1,6 @@
 """Build oracle/liboracle.so from oracle/oracle.c with gcc (FP64, OpenMP, no fast-math).
 
-Test infrastructure only: the oracle is the checker, never part of the product path.
+Test infrastructure only: the oracle verifies the product path and is never part of it.
 """
 from __future__ import annotations
 

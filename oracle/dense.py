@@ -1,4 +1,4 @@
-"""Dense-matrix checker for n <= 10 (TEST INFRASTRUCTURE ONLY).
+"""Dense-matrix cross-check for n <= 10 (TEST INFRASTRUCTURE ONLY).
 
 Builds H_C and H_D as explicit 2^n x 2^n matrices from Kronecker products of
 2x2 Pauli matrices, with qubit 0 as the LAST (rightmost) factor so that it is

@@ -5,7 +5,7 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 from ``oracle/oracle.c`` by ``oracle/build.py``) and adds:
 
   * the AQA / QAOA parameter schedules, written from Sec. III.B and Appendix A;
-  * a dense-matrix checker (Kronecker products + ``scipy.linalg.expm``) for
+  * a dense-matrix cross-check (Kronecker products + ``scipy.linalg.expm``) for
     n <= 10, independent of the bit-loop code in ``oracle.c``;
   * central finite differences with a Richardson pair for gradients.
 
