@@ -1233,10 +1233,30 @@ struct BatchCfg {
 
 __device__ __forceinline__ uint32_t bswz(uint32_t z, int G) { return lds_swizzle(z, G); }
 
-// exp(-i beta sigma^x) on every qubit of an LDS-resident state of 2^nb elements
-// (bits 0..nb-1), in register blocks of 5 bits.
+// exp(-i beta sigma^x) / cos(beta) on the NB index bits of 2^NB register values,
+// t = tan(beta): the pair (a, b) becomes (a - i t b, b - i t a).  The scan applies
+// the factor cos(beta)^{2n} to the reduced sums instead of to every amplitude.
+template <typename Real, int NB>
+__device__ __forceinline__ void reg_mix(typename V2T<Real>::type (&v)[1 << NB], Real t) {
+#pragma unroll
+    for (int k = 0; k < NB; k++) {
+#pragma unroll
+        for (int r = 0; r < (1 << NB); r++) {
+            if (r & (1 << k)) continue;
+            const int r2 = r | (1 << k);
+            const Real ar = v[r].x, ai = v[r].y, br = v[r2].x, bi = v[r2].y;
+            v[r].x = ar + t * bi;
+            v[r].y = ai - t * br;
+            v[r2].x = br + t * ai;
+            v[r2].y = bi - t * ar;
+        }
+    }
+}
+
+// exp(-i beta sigma^x) / cos(beta) on every qubit of an LDS-resident state of 2^nb
+// elements (bits 0..nb-1), in register blocks of 5 bits; t = tan(beta).
 template <typename Real, int NTH>
-__device__ void lds_mixer(typename V2T<Real>::type* st, int nb, Real c, Real s) {
+__device__ void lds_mixer(typename V2T<Real>::type* st, int nb, Real t) {
     using V2 = typename V2T<Real>::type;
     constexpr int G = BatchCfg<Real>::G;
     const int nblk = (nb + 4) / 5;
@@ -1250,9 +1270,10 @@ __device__ void lds_mixer(typename V2T<Real>::type* st, int nb, Real c, Real s) 
         const uint32_t nq = 1u << (nb - 5);
         for (uint32_t q = threadIdx.x; q < nq; q += NTH) {
             const uint32_t zb = (q & ((1u << a0) - 1u)) | ((q >> a0) << (a0 + 5));
+            const uint32_t bz = bswz(zb, G);
             V2 v[32];
 #pragma unroll
-            for (int r = 0; r < 32; r++) v[r] = st[bswz(zb | ((uint32_t)r << a0), G)];
+            for (int r = 0; r < 32; r++) v[r] = st[bz ^ bswz((uint32_t)r << a0, G)];
 #pragma unroll
             for (int k = 0; k < 5; k++) {
                 if (!((act >> k) & 1u)) continue;
@@ -1261,14 +1282,14 @@ __device__ void lds_mixer(typename V2T<Real>::type* st, int nb, Real c, Real s) 
                     if (r & (1 << k)) continue;
                     const int r2 = r | (1 << k);
                     const Real ar = v[r].x, ai = v[r].y, br = v[r2].x, bi = v[r2].y;
-                    v[r].x = c * ar + s * bi;
-                    v[r].y = c * ai - s * br;
-                    v[r2].x = c * br + s * ai;
-                    v[r2].y = c * bi - s * ar;
+                    v[r].x = ar + t * bi;
+                    v[r].y = ai - t * br;
+                    v[r2].x = br + t * ai;
+                    v[r2].y = bi - t * ar;
                 }
             }
 #pragma unroll
-            for (int r = 0; r < 32; r++) st[bswz(zb | ((uint32_t)r << a0), G)] = v[r];
+            for (int r = 0; r < 32; r++) st[bz ^ bswz((uint32_t)r << a0, G)] = v[r];
         }
         __syncthreads();
     }
@@ -1284,8 +1305,9 @@ __global__ void __launch_bounds__(NTH, MINW) k_batch_scan(const BatchArgs a) {
     using V2 = typename V2T<Real>::type;
     constexpr int G = BatchCfg<Real>::G;
     constexpr int U = kBatchUnroll;
+    static_assert(S >= 10 && S <= 15, "slice rounds assume 10 <= S <= 15");
     __shared__ V2 st[1 << S];
-    __shared__ double2 lut[LUTN];
+    __shared__ V2 lut[LUTN];  // 2^{-n/2} exp(-i gamma E), rounded once to the storage type
     __shared__ double red[NTH / 64][2];
     __shared__ int s_unit;
     const int t = threadIdx.x;
@@ -1309,7 +1331,8 @@ __global__ void __launch_bounds__(NTH, MINW) k_batch_scan(const BatchArgs a) {
             for (int m = t; m < in.lut_n; m += NTH) {
                 double sn, cs;
                 sincos(gam * (double)(in.lut_lo + m), &sn, &cs);
-                lut[m] = make_double2(amp0 * cs, -amp0 * sn);
+                lut[m].x = (Real)(amp0 * cs);
+                lut[m].y = (Real)(-amp0 * sn);
             }
             __syncthreads();
         }
@@ -1323,11 +1346,7 @@ __global__ void __launch_bounds__(NTH, MINW) k_batch_scan(const BatchArgs a) {
                     x[j] = z < lim ? X[base + z] : (uint16_t)0;
                 }
 #pragma unroll
-                for (int j = 0; j < U; j++) {
-                    const double2 w = lut[x[j]];
-                    out[j].x = (Real)w.x;
-                    out[j].y = (Real)w.y;
-                }
+                for (int j = 0; j < U; j++) out[j] = lut[x[j]];
             } else {
                 double e[U];
 #pragma unroll
@@ -1346,13 +1365,15 @@ __global__ void __launch_bounds__(NTH, MINW) k_batch_scan(const BatchArgs a) {
             }
         };
         // <H_C> and P_gs terms of U entries
-        auto obs_block = [&](uint64_t base, uint32_t z0, uint32_t lim, const V2 (&v)[U], double& r_e, double& r_p) {
+        // (amplitude j sits at index z0 + j NTH; its energy is that of index (z0 + j NTH) ^ fl)
+        auto obs_block = [&](uint64_t base, uint32_t z0, uint32_t lim, uint32_t fl, const V2 (&v)[U], double& r_e,
+                             double& r_p) {
             if (intE) {
                 uint16_t x[U];
 #pragma unroll
                 for (int j = 0; j < U; j++) {
                     const uint32_t z = z0 + j * NTH;
-                    x[j] = z < lim ? X[base + z] : (uint16_t)0;
+                    x[j] = z < lim ? X[base + (z ^ fl)] : (uint16_t)0;
                 }
 #pragma unroll
                 for (int j = 0; j < U; j++) {
@@ -1366,7 +1387,7 @@ __global__ void __launch_bounds__(NTH, MINW) k_batch_scan(const BatchArgs a) {
 #pragma unroll
                 for (int j = 0; j < U; j++) {
                     const uint32_t z = z0 + j * NTH;
-                    e[j] = z < lim ? E[base + z] : 0.0;
+                    e[j] = z < lim ? E[base + (z ^ fl)] : 0.0;
                 }
 #pragma unroll
                 for (int j = 0; j < U; j++) {
@@ -1378,8 +1399,18 @@ __global__ void __launch_bounds__(NTH, MINW) k_batch_scan(const BatchArgs a) {
             }
         };
         for (int b = 0; b < a.nb; b++) {
-            const double beta = a.betas[b];
-            const Real c = (Real)cos(beta), s = (Real)sin(beta);
+            // beta -> beta + pi multiplies the state by (-1)^n, and beta -> beta + pi/2
+            // applies -i sigma^x to every qubit, which moves the amplitude of z to the
+            // complement of z.  So beta is reduced to |beta| <= pi/4, the mixers run in
+            // the tangent form (|tan| <= 1), the tables are read at z ^ fl, and the sums
+            // take the factor cos(beta)^{2n} at the end.
+            double bb = remainder(a.betas[b], M_PI);
+            uint32_t fl = 0u;
+            if (fabs(bb) > 0.25 * M_PI) {
+                bb -= copysign(0.5 * M_PI, bb);
+                fl = (uint32_t)((1ull << n) - 1ull);
+            }
+            const Real tq = (Real)tan(bb);
             double r_e = 0.0, r_p = 0.0;
             if (n <= S) {
                 const uint32_t N = 1u << n;
@@ -1392,7 +1423,7 @@ __global__ void __launch_bounds__(NTH, MINW) k_batch_scan(const BatchArgs a) {
                 }
                 __syncthreads();
                 if (n >= 5) {
-                    lds_mixer<Real, NTH>(st, n, c, s);
+                    lds_mixer<Real, NTH>(st, n, tq);
                 } else {
                     if (t == 0) {  // tiny states: plain pair loops
                         for (int q = 0; q < n; q++)
@@ -1401,10 +1432,10 @@ __global__ void __launch_bounds__(NTH, MINW) k_batch_scan(const BatchArgs a) {
                                 V2& x = st[bswz(z, G)];
                                 V2& y = st[bswz(z | (1u << q), G)];
                                 const Real ar = x.x, ai = x.y, br = y.x, bi = y.y;
-                                x.x = c * ar + s * bi;
-                                x.y = c * ai - s * br;
-                                y.x = c * br + s * ai;
-                                y.y = c * bi - s * ar;
+                                x.x = ar + tq * bi;
+                                x.y = ai - tq * br;
+                                y.x = br + tq * ai;
+                                y.y = bi - tq * ar;
                             }
                     }
                     __syncthreads();
@@ -1417,22 +1448,66 @@ __global__ void __launch_bounds__(NTH, MINW) k_batch_scan(const BatchArgs a) {
                         if (z < N) v[j] = st[bswz(z, G)];
                         else v[j].x = v[j].y = (Real)0;
                     }
-                    obs_block(0, z0, N, v, r_e, r_p);
+                    obs_block(0, z0, N, fl, v, r_e, r_p);
                 }
             } else {
-                // low S bits slice by slice in LDS, written to this workgroup's slot
+                // low S bits slice by slice, written to this workgroup's slot: bits
+                // S-5..S-1 in registers as the phases are formed, bits 0..4 in LDS,
+                // bits 5..S-6 on the way from LDS to the slot
                 const int nh = n - S;
+                constexpr int LB = S - 5;
+                constexpr int MB = S - 10;
                 for (uint32_t sl = 0; sl < (1u << nh); sl++) {
                     const uint64_t off = (uint64_t)sl << S;
-                    for (uint32_t z0 = t; z0 < (1u << S); z0 += NTH * U) {
-                        V2 v[U];
-                        phi_block(off, z0, 1u << S, v);
+                    if (!intE) {
+                        for (uint32_t z0 = t; z0 < (1u << S); z0 += NTH * U) {
+                            V2 v[U];
+                            phi_block(off, z0, 1u << S, v);
 #pragma unroll
-                        for (int j = 0; j < U; j++) st[bswz(z0 + j * NTH, G)] = v[j];
+                            for (int j = 0; j < U; j++) st[bswz(z0 + j * NTH, G)] = v[j];
+                        }
+                        __syncthreads();
+                    }
+                    const uint16_t* Xs = X + off;  // uniform bases, 32-bit lane offsets
+                    V2* Ss = slot + off;
+                    for (uint32_t l = t; l < (1u << LB); l += NTH) {
+                        const uint32_t bl = bswz(l, G);
+                        V2 v[32];
+                        if (intE) {
+                            uint16_t x[32];
+#pragma unroll
+                            for (int r = 0; r < 32; r++) x[r] = Xs[l | ((uint32_t)r << LB)];
+#pragma unroll
+                            for (int r = 0; r < 32; r++) v[r] = lut[x[r]];
+                        } else {
+#pragma unroll
+                            for (int r = 0; r < 32; r++) v[r] = st[bl ^ bswz((uint32_t)r << LB, G)];
+                        }
+                        reg_mix<Real, 5>(v, tq);
+#pragma unroll
+                        for (int r = 0; r < 32; r++) st[bl ^ bswz((uint32_t)r << LB, G)] = v[r];
                     }
                     __syncthreads();
-                    lds_mixer<Real, NTH>(st, S, c, s);
-                    for (uint32_t z = t; z < (1u << S); z += NTH) slot[off + z] = st[bswz(z, G)];
+                    for (uint32_t q = t; q < (1u << LB); q += NTH) {
+                        const uint32_t bq = bswz(q << 5, G);
+                        V2 v[32];
+#pragma unroll
+                        for (int r = 0; r < 32; r++) v[r] = st[bq ^ bswz((uint32_t)r, G)];
+                        reg_mix<Real, 5>(v, tq);
+#pragma unroll
+                        for (int r = 0; r < 32; r++) st[bq ^ bswz((uint32_t)r, G)] = v[r];
+                    }
+                    __syncthreads();
+                    for (uint32_t g = t; g < (1u << (S - MB)); g += NTH) {
+                        const uint32_t zb = (g & 31u) | ((g >> 5) << (5 + MB));
+                        const uint32_t bz = bswz(zb, G);
+                        V2 v[1 << MB];
+#pragma unroll
+                        for (int r = 0; r < (1 << MB); r++) v[r] = st[bz ^ bswz((uint32_t)r << 5, G)];
+                        reg_mix<Real, MB>(v, tq);
+#pragma unroll
+                        for (int r = 0; r < (1 << MB); r++) Ss[zb | ((uint32_t)r << 5)] = v[r];
+                    }
                     __syncthreads();
                 }
                 // high bits: each thread holds the 2^nh amplitudes of one low index
@@ -1440,7 +1515,7 @@ __global__ void __launch_bounds__(NTH, MINW) k_batch_scan(const BatchArgs a) {
                     V2 v[32];
 #pragma unroll
                     for (int r = 0; r < 32; r++)
-                        if (r < (1 << nh)) v[r] = slot[((uint64_t)r << S) | l];
+                        if (r < (1 << nh)) v[r] = slot[((uint32_t)r << S) | l];
 #pragma unroll
                     for (int k = 0; k < 5; k++) {
                         if (k >= nh) continue;
@@ -1449,10 +1524,10 @@ __global__ void __launch_bounds__(NTH, MINW) k_batch_scan(const BatchArgs a) {
                             if ((r & (1 << k)) || r >= (1 << nh)) continue;
                             const int r2 = r | (1 << k);
                             const Real ar = v[r].x, ai = v[r].y, br = v[r2].x, bi = v[r2].y;
-                            v[r].x = c * ar + s * bi;
-                            v[r].y = c * ai - s * br;
-                            v[r2].x = c * br + s * ai;
-                            v[r2].y = c * bi - s * ar;
+                            v[r].x = ar + tq * bi;
+                            v[r].y = ai - tq * br;
+                            v[r2].x = br + tq * ai;
+                            v[r2].y = bi - tq * ar;
                         }
                     }
                     if (intE) {
@@ -1461,7 +1536,7 @@ __global__ void __launch_bounds__(NTH, MINW) k_batch_scan(const BatchArgs a) {
                             uint16_t x[U];
 #pragma unroll
                             for (int j = 0; j < U; j++)
-                                x[j] = r0 + j < (1 << nh) ? X[((uint64_t)(r0 + j) << S) | l] : (uint16_t)0;
+                                x[j] = r0 + j < (1 << nh) ? X[(((uint32_t)(r0 + j) << S) | l) ^ fl] : (uint16_t)0;
 #pragma unroll
                             for (int j = 0; j < U; j++) {
                                 const int r = r0 + j;
@@ -1476,7 +1551,7 @@ __global__ void __launch_bounds__(NTH, MINW) k_batch_scan(const BatchArgs a) {
                         for (int r = 0; r < 32; r++) {
                             if (r >= (1 << nh)) continue;
                             const double p2 = (double)v[r].x * v[r].x + (double)v[r].y * v[r].y;
-                            const double e = E[((uint64_t)r << S) | l];
+                            const double e = E[(((uint32_t)r << S) | l) ^ fl];
                             r_e += e * p2;
                             if (fabs(e - in.emin) <= in.etol) r_p += p2;
                         }
@@ -1501,9 +1576,10 @@ __global__ void __launch_bounds__(NTH, MINW) k_batch_scan(const BatchArgs a) {
                     se += red[w][0];
                     sp += red[w][1];
                 }
+                const double cb = cos(bb), sc = pow(cb * cb, (double)n);  // the deferred cos(beta)^{2n}
                 const uint64_t o = ((uint64_t)a.unit_inst[u] * a.ng + a.unit_gam[u]) * a.nb + b;
-                a.out_e[o] = se;
-                a.out_p[o] = sp;
+                a.out_e[o] = se * sc;
+                a.out_p[o] = sp * sc;
             }
             __syncthreads();
         }

@@ -543,6 +543,26 @@ def test_batch_scan_variants(sv, orc, wide):
         assert np.max(np.abs(pg[i] - rpg)) <= PROB_TOL["c64"], (i, inst["n"])
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_scan_any_beta(sv, orc, dtype):
+    """Mixer angles off the half-open grid: negative, at and across +-pi/4 and
+    +-pi/2 (where cos beta = 0), beyond pi, on states that fit one LDS slice and
+    states that do not."""
+    betas = np.array([0.0, -0.3, math.pi / 4, -math.pi / 4, 0.8, math.pi / 2, -math.pi / 2, 2.0, -2.6,
+                      math.pi, 7.3, -11.0])
+    gams = np.array([0.0, 0.37, -1.9])
+    ns = [2, 6, 11, 13, 14, 15, 17]
+    insts = [I.regular3_pm1(n, 590 + k) if n >= 4 else instance_for(n, "real", 590 + k) for k, n in enumerate(ns)]
+    insts.append(I.random_real(16, 30, 591))
+    Hs = [sv.Ising.from_instance(x) for x in insts]
+    en, pg = sv.batch_p1_scan(Hs, gams, betas, dtype=dtype)
+    for i, inst in enumerate(insts):
+        ren, rpg = _batch_oracle(orc, inst, gams, betas)
+        tol = 1e-6 * max(orc.coeff_scale(inst), 1.0)
+        assert np.max(np.abs(en[i] - ren)) <= tol, (i, inst["n"])
+        assert np.max(np.abs(pg[i] - rpg)) <= PROB_TOL[dtype], (i, inst["n"])
+
+
 def test_batch_scan_closed_form_full_grid(sv, orc):
     """32 x 32 grid of the batched workload on 64 instances: <H_C> at every point
     against the depth-one closed form (test_oracle_pins.p1_closed_form_energy)."""
