@@ -57,8 +57,8 @@ std::map<std::string, int> g_knobs = {
     {"snake", 1},     // 1: the contiguous tile group takes a middle slot of the layer's group order
     {"dpp", 1},       // 1: one active bit may be butterflied across lanes to save a layout
     {"ldsswz", 4},    // LDS slot swizzle width of the tile passes (3..5)
-    {"batchwide", 1}, // complex64 batch scan: 1 = 2^14 LDS states, eight waves; 0 = four waves;
-                      // 2 = 2^13 LDS states, four waves, two workgroups per CU
+    {"batchwide", 2}, // complex64 batch scan: 2 = 2^13 LDS states, four waves, two workgroups
+                      // per CU; 1 = 2^14 LDS states, eight waves; 0 = 2^14, four waves
     {"c64t13", 0},    // complex64 one-vector programs: 1 = 13-bit tiles (four waves), 0 = 14-bit tiles
     {"c64occ", 1},    // complex64 14-bit tiles: 1 = no lane position 4, two workgroups per CU
     {"c64g4", 1},     // complex64 two-vector passes: 1 = four waves per SIMD (two workgroups per CU)

@@ -1598,9 +1598,9 @@ int launch_batch_energy(const BatchArgs& a, int max_n, void* stream) {
 
 // Variants: complex128 2^13-amplitude LDS states, four waves; complex64 2^14 states with eight
 // waves (wide = 1) or four (wide = 0), one workgroup per CU; complex64 2^13 states with four
-// waves and a 512-entry phase table (wide = 2), two workgroups per CU.
+// waves (wide = 2), two workgroups per CU.  Phase tables hold 1024 entries.
 int batch_lds_bits(int dtype, int wide) { return dtype == 2 ? 13 : (wide == 2 ? 13 : 14); }
-int batch_lut_cap(int dtype, int wide) { return (dtype != 2 && wide == 2) ? 512 : 1024; }
+int batch_lut_cap(int, int) { return 1024; }
 
 int launch_batch_scan(int dtype, const BatchArgs& a, int grid, int wide, void* stream) {
     if (dtype == 2)
@@ -1608,7 +1608,7 @@ int launch_batch_scan(int dtype, const BatchArgs& a, int grid, int wide, void* s
     else if (wide == 1)
         hipLaunchKernelGGL((k_batch_scan<float, 512, 14, 1024>), dim3(grid), dim3(512), 0, (hipStream_t)stream, a);
     else if (wide == 2)
-        hipLaunchKernelGGL((k_batch_scan<float, 256, 13, 512, 2>), dim3(grid), dim3(256), 0, (hipStream_t)stream, a);
+        hipLaunchKernelGGL((k_batch_scan<float, 256, 13, 1024, 2>), dim3(grid), dim3(256), 0, (hipStream_t)stream, a);
     else
         hipLaunchKernelGGL((k_batch_scan<float, 256, 14, 1024>), dim3(grid), dim3(256), 0, (hipStream_t)stream, a);
     return (int)hipGetLastError();
