@@ -1233,6 +1233,14 @@ struct BatchCfg {
 
 __device__ __forceinline__ uint32_t bswz(uint32_t z, int G) { return lds_swizzle(z, G); }
 
+// Hides a per-thread value from loop-invariant code motion: the block addresses
+// derived from it are then formed next to their use instead of being hoisted out
+// of the slice and beta loops and kept live (and spilled) across them.
+__device__ __forceinline__ uint32_t opaque(uint32_t x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // exp(-i beta sigma^x) / cos(beta) on the NB index bits of 2^NB register values,
 // t = tan(beta): the pair (a, b) becomes (a - i t b, b - i t a).  The scan applies
 // the factor cos(beta)^{2n} to the reduced sums instead of to every amplitude.
@@ -1471,7 +1479,7 @@ __global__ void __launch_bounds__(NTH, MINW) k_batch_scan(const BatchArgs a) {
                     const uint16_t* Xs = X + off;  // uniform bases, 32-bit lane offsets
                     V2* Ss = slot + off;
                     for (uint32_t l = t; l < (1u << LB); l += NTH) {
-                        const uint32_t bl = bswz(l, G);
+                        const uint32_t bl = opaque(bswz(l, G));
                         V2 v[32];
                         if (intE) {
                             uint16_t x[32];
@@ -1489,7 +1497,7 @@ __global__ void __launch_bounds__(NTH, MINW) k_batch_scan(const BatchArgs a) {
                     }
                     __syncthreads();
                     for (uint32_t q = t; q < (1u << LB); q += NTH) {
-                        const uint32_t bq = bswz(q << 5, G);
+                        const uint32_t bq = opaque(bswz(q << 5, G));
                         V2 v[32];
 #pragma unroll
                         for (int r = 0; r < 32; r++) v[r] = st[bq ^ bswz((uint32_t)r, G)];
@@ -1500,7 +1508,7 @@ __global__ void __launch_bounds__(NTH, MINW) k_batch_scan(const BatchArgs a) {
                     __syncthreads();
                     for (uint32_t g = t; g < (1u << (S - MB)); g += NTH) {
                         const uint32_t zb = (g & 31u) | ((g >> 5) << (5 + MB));
-                        const uint32_t bz = bswz(zb, G);
+                        const uint32_t bz = opaque(bswz(zb, G));
                         V2 v[1 << MB];
 #pragma unroll
                         for (int r = 0; r < (1 << MB); r++) v[r] = st[bz ^ bswz((uint32_t)r << 5, G)];
@@ -1511,7 +1519,8 @@ __global__ void __launch_bounds__(NTH, MINW) k_batch_scan(const BatchArgs a) {
                     __syncthreads();
                 }
                 // high bits: each thread holds the 2^nh amplitudes of one low index
-                for (uint32_t l = t; l < (1u << S); l += NTH) {
+                for (uint32_t l0 = t; l0 < (1u << S); l0 += NTH) {
+                    const uint32_t l = opaque(l0);
                     V2 v[32];
 #pragma unroll
                     for (int r = 0; r < 32; r++)
