@@ -246,7 +246,9 @@ def main():
             ns = np.array([x["n"] for x in insts], dtype=np.float64)
             items = len(insts) * len(gb) * len(bb)
             upd = float(np.sum(2.0 ** ns * (ns + 1))) * len(gb) * len(bb)
-            flops = float(np.sum(2.0 ** ns * (8 * ns + 6))) * len(gb) * len(bb)
+            # floating-point work the kernel executes per amplitude: two FMAs per qubit in the
+            # tangent-form mixer (4 flops) and |psi|^2, E |psi|^2 for the sums (6 flops)
+            flops = float(np.sum(2.0 ** ns * (4 * ns + 6))) * len(gb) * len(bb)
             peak = 157.3e12 if dt == "c64" else 78.6e12
             extras[f"batch_scan_{dt}"] = {"ms": round(msb, 3), "items": items, "items_per_s": items / (msb * 1e-3),
                                           "amp_updates_per_s": upd / (msb * 1e-3),
