@@ -59,6 +59,8 @@ std::map<std::string, int> g_knobs = {
     {"ldsswz", 4},    // LDS slot swizzle width of the tile passes (3..5)
     {"batchwide", 2}, // complex64 batch scan: 2 = 2^13 LDS states, four waves, two workgroups
                       // per CU; 1 = 2^14 LDS states, eight waves; 0 = 2^14, four waves
+    {"batch128", 1},  // complex128 batch scan (2^13 LDS states, one workgroup per CU): 1 = eight
+                      // waves, 0 = four
     {"c64t13", 0},    // complex64 one-vector programs: 1 = 13-bit tiles (four waves), 0 = 14-bit tiles
     {"c64occ", 1},    // complex64 14-bit tiles: 1 = no lane position 4, two workgroups per CU
     {"c64g4", 1},     // complex64 two-vector passes: 1 = four waves per SIMD (two workgroups per CU)
@@ -140,6 +142,8 @@ extern "C" int sv_tune_set(const char* name, int value) {
     if (std::string(name) == "c64g14" && (value < 0 || value > 2)) return fail(SV_ERR_ARG, "c64g14 must be in [0, 2]");
     if (std::string(name) == "batchwide" && (value < 0 || value > 2))
         return fail(SV_ERR_ARG, "batchwide must be in [0, 2]");
+    if (std::string(name) == "batch128" && (value < 0 || value > 1))
+        return fail(SV_ERR_ARG, "batch128 must be 0 or 1");
     if (std::string(name) == "stagger" && (value < 0 || value > 64)) return fail(SV_ERR_ARG, "stagger must be in [0, 64]");
     it->second = value;
     return SV_OK;
@@ -2152,7 +2156,7 @@ extern "C" int sv_batch_p1_scan(int n_inst, const sv_ising* insts, int n_gamma, 
         if (!std::isfinite(gammas[a])) return fail(SV_ERR_NUMERIC, "sv_batch_p1_scan: gamma %d not finite", a);
     for (int b = 0; b < n_beta; b++)
         if (!std::isfinite(betas[b])) return fail(SV_ERR_NUMERIC, "sv_batch_p1_scan: beta %d not finite", b);
-    const int wide = dtype == SV_C64 ? knob_for("batchwide", (int)dtype, 0) : 0;
+    const int wide = dtype == SV_C64 ? knob_for("batchwide", (int)dtype, 0) : knob_for("batch128", (int)dtype, 0);
     const int lut_cap = batch_lut_cap((int)dtype, wide);
     const int S = batch_lds_bits((int)dtype, wide);
     const int nmax_batch = S + 5;  // the high bits of a state fit one thread's 32 registers

@@ -1605,14 +1605,17 @@ int launch_batch_energy(const BatchArgs& a, int max_n, void* stream) {
     return (int)hipGetLastError();
 }
 
-// Variants: complex128 2^13-amplitude LDS states, four waves; complex64 2^14 states with eight
+// Variants: complex128 2^13-amplitude LDS states, four waves (wide = 0) or eight (wide = 1);
+// complex64 2^14 states with eight
 // waves (wide = 1) or four (wide = 0), one workgroup per CU; complex64 2^13 states with four
 // waves (wide = 2), two workgroups per CU.  Phase tables hold 1024 entries.
 int batch_lds_bits(int dtype, int wide) { return dtype == 2 ? 13 : (wide == 2 ? 13 : 14); }
 int batch_lut_cap(int, int) { return 1024; }
 
 int launch_batch_scan(int dtype, const BatchArgs& a, int grid, int wide, void* stream) {
-    if (dtype == 2)
+    if (dtype == 2 && wide == 1)
+        hipLaunchKernelGGL((k_batch_scan<double, 512, 13, 1024>), dim3(grid), dim3(512), 0, (hipStream_t)stream, a);
+    else if (dtype == 2)
         hipLaunchKernelGGL((k_batch_scan<double, 256, 13, 1024>), dim3(grid), dim3(256), 0, (hipStream_t)stream, a);
     else if (wide == 1)
         hipLaunchKernelGGL((k_batch_scan<float, 512, 14, 1024>), dim3(grid), dim3(512), 0, (hipStream_t)stream, a);

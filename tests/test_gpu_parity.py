@@ -522,25 +522,29 @@ def test_batch_scan_vs_oracle(sv, orc, dtype):
         assert np.max(np.abs(pg[i] - rpg)) <= PROB_TOL[dtype], (i, inst["n"])
 
 
-@pytest.mark.parametrize("wide", [0, 1])
-def test_batch_scan_variants(sv, orc, wide):
-    """The other complex64 batch kernels (one workgroup per CU with 2^14 LDS states,
-    four or eight waves) against the oracle."""
+@pytest.mark.parametrize("dtype,knob,val", [("c64", "batchwide", 0), ("c64", "batchwide", 1),
+                                            ("c64", "batchwide", 2), ("c128", "batch128", 0),
+                                            ("c128", "batch128", 1)])
+def test_batch_scan_variants(sv, orc, dtype, knob, val):
+    """Every batch kernel variant (complex64: one workgroup per CU with 2^14 LDS
+    states and four or eight waves, or two per CU with 2^13; complex128: four or
+    eight waves) against the oracle."""
     ns = [3, 9, 12, 13, 14, 15, 17, 18]
     insts = [I.regular3_pm1(n, 520 + k) if n >= 4 else instance_for(n, "real", 520 + k) for k, n in enumerate(ns)]
     insts.append(I.random_real(14, 25, 78))
     gam, bet = I.batch_grid(4, 5)
     Hs = [sv.Ising.from_instance(x) for x in insts]
-    sv.tune_set("batchwide", wide)
+    old = sv.tune_get(knob)
+    sv.tune_set(knob, val)
     try:
-        en, pg = sv.batch_p1_scan(Hs, gam, bet, dtype="c64")
+        en, pg = sv.batch_p1_scan(Hs, gam, bet, dtype=dtype)
     finally:
-        sv.tune_set("batchwide", 2)
+        sv.tune_set(knob, old)
     for i, inst in enumerate(insts):
         ren, rpg = _batch_oracle(orc, inst, gam, bet)
         tol = 1e-6 * max(orc.coeff_scale(inst), 1.0)
         assert np.max(np.abs(en[i] - ren)) <= tol, (i, inst["n"])
-        assert np.max(np.abs(pg[i] - rpg)) <= PROB_TOL["c64"], (i, inst["n"])
+        assert np.max(np.abs(pg[i] - rpg)) <= PROB_TOL[dtype], (i, inst["n"])
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
