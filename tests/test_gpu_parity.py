@@ -567,6 +567,28 @@ def test_batch_scan_any_beta(sv, orc, dtype):
         assert np.max(np.abs(pg[i] - rpg)) <= PROB_TOL[dtype], (i, inst["n"])
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_scan_integer_range_beyond_table(sv, orc, dtype):
+    """Integer-valued instances whose energy range exceeds the 1024-entry phase
+    table take the FP64 energy-table path, in and above one LDS slice, next to
+    instances that use the table."""
+    insts = []
+    for k, n in enumerate([9, 13, 16]):
+        base = I.regular3_pm1(n, 610 + k)
+        insts.append(dict(base, J=np.asarray(base["J"]) * 40.0, h=np.asarray(base["h"]) * 7.0))
+        insts.append(I.regular3_pm1(n, 620 + k))
+    for x in insts[::2]:
+        assert 2 * (np.sum(np.abs(x["h"])) + np.sum(np.abs(x["J"]))) + 1 > 1024
+    gam, bet = np.array([0.0, 0.013, -0.21]), np.array([0.1, 0.9, -1.4])
+    Hs = [sv.Ising.from_instance(x) for x in insts]
+    en, pg = sv.batch_p1_scan(Hs, gam, bet, dtype=dtype)
+    for i, inst in enumerate(insts):
+        ren, rpg = _batch_oracle(orc, inst, gam, bet)
+        tol = 1e-6 * max(orc.coeff_scale(inst), 1.0)
+        assert np.max(np.abs(en[i] - ren)) <= tol, (i, inst["n"])
+        assert np.max(np.abs(pg[i] - rpg)) <= PROB_TOL[dtype], (i, inst["n"])
+
+
 def test_batch_scan_closed_form_full_grid(sv, orc):
     """32 x 32 grid of the batched workload on 64 instances: <H_C> at every point
     against the depth-one closed form (test_oracle_pins.p1_closed_form_energy)."""
