@@ -472,3 +472,117 @@ def _sample(f, s, default):
     if arr.shape != s.shape:
         raise ValueError("schedule array must have one value per grid point")
     return arr
+
+
+# ----------------------------------------------------------------------------- block-separable instances
+def coupling_components(inst):
+    """Qubit sets of the connected components of the coupling graph (every listed
+    pair (i, j) joins its two qubits, whatever J_ij), each sorted ascending;
+    the components are ordered by their smallest qubit."""
+    n = int(inst["n"])
+    parent = list(range(n))
+
+    def find(a):
+        while parent[a] != a:
+            parent[a] = parent[parent[a]]
+            a = parent[a]
+        return a
+
+    for i, j in zip(np.asarray(inst["ei"]).tolist(), np.asarray(inst["ej"]).tolist()):
+        ri, rj = find(int(i)), find(int(j))
+        if ri != rj:
+            parent[max(ri, rj)] = min(ri, rj)
+    groups = {}
+    for q in range(n):
+        groups.setdefault(find(q), []).append(q)
+    return [sorted(g) for _, g in sorted(groups.items())]
+
+
+def sub_instance(inst, qubits):
+    """The part of Eq. HC that acts on the given qubits (a coupling component),
+    relabelled so that qubits[r] becomes local qubit r."""
+    qubits = [int(q) for q in qubits]
+    local = {q: r for r, q in enumerate(qubits)}
+    h = np.asarray(inst["h"], dtype=np.float64)[qubits]
+    ei, ej, J = [], [], []
+    for i, j, v in zip(np.asarray(inst["ei"]).tolist(), np.asarray(inst["ej"]).tolist(),
+                       np.asarray(inst["J"]).tolist()):
+        if int(i) in local:
+            ei.append(local[int(i)])
+            ej.append(local[int(j)])
+            J.append(v)
+    return {"n": len(qubits), "h": h, "ei": np.array(ei, dtype=np.int32), "ej": np.array(ej, dtype=np.int32),
+            "J": np.array(J, dtype=np.float64)}
+
+
+def block_states(inst, gamma, beta):
+    """QAOA state of an instance whose coupling graph splits into small components,
+    as one oracle state per component.  H_C is then a sum of terms on disjoint
+    qubit sets and H_D a sum of single-qubit terms, so every factor of Eq.
+    QAOA_state is a product over the components and the state is the tensor
+    product of the components' own QAOA states (same gamma, beta).
+    Returns [(qubits, psi_b)], psi_b indexed by the component's local bits."""
+    out = []
+    for qs in coupling_components(inst):
+        out.append((qs, qaoa_state(sub_instance(inst, qs), gamma, beta)))
+    return out
+
+
+def block_amplitudes(blocks, zs) -> np.ndarray:
+    """psi(z) = prod_b psi_b(z restricted to the qubits of component b) at the
+    basis indices zs (any n; no full state vector)."""
+    zs = np.asarray(zs, dtype=np.uint64)
+    out = np.ones(len(zs), dtype=np.complex128)
+    for qs, psi in blocks:
+        loc = np.zeros(len(zs), dtype=np.int64)
+        for r, q in enumerate(qs):
+            loc |= (((zs >> np.uint64(q)) & np.uint64(1)).astype(np.int64)) << r
+        out *= psi[loc]
+    return out
+
+
+def block_observables(inst, blocks):
+    """(<H_C>, ground-state probability) of a product over coupling components:
+    <H_C> = sum_b <H_b> (each factor has unit norm), and since E(z) = sum_b E_b(z_b)
+    with the z_b independent, the ground set is the product of the components'
+    ground sets and P_gs = prod_b P_gs,b."""
+    en, pg = 0.0, 1.0
+    for qs, psi in blocks:
+        sub = sub_instance(inst, qs)
+        _, e, p = observables(sub, psi)
+        en += e
+        pg *= p
+    return en, pg
+
+
+def block_grad(inst, gamma, beta):
+    """(f, df/dgamma, df/dbeta) of a component-separable instance: f = sum_b f_b with
+    f_b the QAOA energy of component b at the same (gamma, beta), so the gradient
+    is the sum of the components' forward-mode tangent gradients."""
+    p = len(np.atleast_1d(gamma))
+    f, dg, db = 0.0, np.zeros(p), np.zeros(p)
+    for qs in coupling_components(inst):
+        fb, gb, bb = grad_tangent(sub_instance(inst, qs), gamma, beta)
+        f += fb
+        dg += gb
+        db += bb
+    return f, dg, db
+
+
+def block_aqa_observables(inst, gamma, beta):
+    """Per-step (<H_C>[k], P_gs[k]) of the layer sequence (gamma_k, beta_k) on a
+    component-separable instance, from the components' step-by-step states."""
+    comps = [(qs, sub_instance(inst, qs)) for qs in coupling_components(inst)]
+    states = [plus_state(len(qs)) for qs, _ in comps]
+    gss = [ground(sub) for _, sub in comps]
+    en, pg = [], []
+    for g, b in zip(np.atleast_1d(gamma), np.atleast_1d(beta)):
+        e_sum, p_prod = 0.0, 1.0
+        for c, (qs, sub) in enumerate(comps):
+            states[c] = qaoa_state(sub, [g], [b], psi0=states[c])
+            _, e, p = observables(sub, states[c], gs=gss[c])
+            e_sum += e
+            p_prod *= p
+        en.append(e_sum)
+        pg.append(p_prod)
+    return np.array(en), np.array(pg)

@@ -67,6 +67,8 @@ std::map<std::string, int> g_knobs = {
     {"kc34", 1},      // two-vector passes with 3 or 4 layouts: 1 = straight-line kernels, 0 = layout loop
     {"c64g14", 2},    // complex64 adjoint programs on 14-bit tiles: 1 always, 2 when fewer groups, 0 never
     {"ntinit", 1},    // write-only first passes: 1 = nontemporal stores
+    {"split", 0},     // bits above the contiguous tile: 0 = near-equal groups, 1 = largest groups first
+    {"fail_next_launch", 0},  // 1: the next tile-pass launch reports a launch failure (error-path tests)
 };
 int knob(const char* k) {
     std::lock_guard<std::mutex> g(g_knob_mu);
@@ -106,6 +108,15 @@ int knob_for(const char* k, int dtype, int n) {
     if (it != g_tuned.end()) return it->second;
     return g_knobs[k];
 }
+// Error-path tests: knob fail_next_launch = 1 makes the next tile-pass launch
+// report hipErrorLaunchFailure (nothing is launched), then clears itself.
+bool take_injected_failure() {
+    std::lock_guard<std::mutex> g(g_knob_mu);
+    int& v = g_knobs["fail_next_launch"];
+    if (v == 0) return false;
+    v = 0;
+    return true;
+}
 }  // namespace
 
 extern "C" int sv_tune_load(const char* path) {
@@ -138,6 +149,8 @@ extern "C" int sv_tune_set(const char* name, int value) {
          std::string(name) == "c64occ" || std::string(name) == "c64g4" || std::string(name) == "kc34" ||
          std::string(name) == "ntinit") &&
         (value < 0 || value > 1))
+        return fail(SV_ERR_ARG, "%s must be 0 or 1", name);
+    if ((std::string(name) == "split" || std::string(name) == "fail_next_launch") && (value < 0 || value > 1))
         return fail(SV_ERR_ARG, "%s must be 0 or 1", name);
     if (std::string(name) == "c64g14" && (value < 0 || value > 2)) return fail(SV_ERR_ARG, "c64g14 must be in [0, 2]");
     if (std::string(name) == "batchwide" && (value < 0 || value > 2))
@@ -540,9 +553,10 @@ static std::vector<Geometry> plan_groups(int n, sv_dtype dt, int nv, bool grad =
     const int cmin = std::max(G, knob_for(dt == SV_C128 ? "cmin128" : "cmin64", (int)dt, n));
     const int rest = n - T, gmax = T - cmin;
     const int ng = (rest + gmax - 1) / gmax;
+    const bool largest_first = knob_for("split", (int)dt, n) != 0;
     int lo = T;
     for (int i = 0; i < ng; i++) {
-        int g = rest / ng + (i < rest % ng ? 1 : 0);
+        int g = largest_first ? std::min(gmax, n - lo) : rest / ng + (i < rest % ng ? 1 : 0);
         out.push_back(make_geometry(n, T, R, T - g, lo, g, G, dpp, nv == 1));
         lo += g;
     }
@@ -1215,7 +1229,7 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
             if (genblk[pi][i] >= 0 && !genreal[pi][i]) a.gen_real = 0;
         hipEvent_t ev0;
         const bool prof = prof_begin(s->stream, &ev0);
-        int e = launch_pass((int)s->dt, p.nv, geo.T, a, s->stream);
+        int e = take_injected_failure() ? (int)hipErrorLaunchFailure : launch_pass((int)s->dt, p.nv, geo.T, a, s->stream);
         if (prof) {
             const int nrd = (p.load & 4) ? 0 : __builtin_popcount(p.load & 3);
             const int nwr = __builtin_popcount(p.store & 3);

@@ -267,7 +267,10 @@ __device__ __forceinline__ void mix_round(Real (&vr)[NV][1 << R], Real (&vi)[NV]
                 for (int r = 0; r < NR; r++) {
                     if (r & (1 << k)) continue;
                     const int r2 = r | (1 << k);
-                    // pair term in the storage precision, summed in FP64
+                    // pair term in the storage precision, summed in FP64 (FP64 products
+                    // change the complex64 gradient by ~1e-10 of the coefficient scale, far
+                    // below the f32 rounding of the stored vectors, and spill the
+                    // four-waves-per-SIMD kernels)
                     const Real q = vr[1][r] * vi[0][r2] - vi[1][r] * vr[0][r2] + vr[1][r2] * vi[0][r] -
                                    vi[1][r2] * vr[0][r];
                     gb += (double)q;

@@ -190,3 +190,24 @@ def linear_ramp_params(p: int, tau: float = 0.5):
 def uniform_params(p: int, seed: int, lo: float = -1.0, hi: float = 1.0):
     rng = _rng(seed)
     return rng.uniform(lo, hi, size=p), rng.uniform(lo, hi, size=p)
+
+
+def block_instance(n: int, seed: int, block: int = 5) -> dict:
+    """Ising instance whose coupling graph is a union of disjoint cliques: a seeded
+    random permutation of the n qubits is cut into consecutive blocks of `block`
+    qubits (the last one takes the remainder), every pair inside a block is
+    coupled with J uniform integer in [-2, 2] (zeros kept), h_i uniform in
+    {-1, 0, 1}.  The blocks scatter over all bit positions, so at full size every
+    tile group holds qubits of coupled pairs.  Only random draws."""
+    rng = _rng(seed)
+    perm = rng.permutation(n)
+    edges = []
+    for b0 in range(0, n, block):
+        qs = np.sort(perm[b0:b0 + block])
+        for a in range(len(qs)):
+            for c in range(a + 1, len(qs)):
+                edges.append((int(qs[a]), int(qs[c])))
+    edges = np.array(sorted(edges), dtype=np.int64).reshape(-1, 2)
+    J = rng.integers(-2, 3, size=len(edges)).astype(np.float64)
+    h = rng.integers(-1, 2, size=n).astype(np.float64)
+    return make_instance(n, edges, h, J)

@@ -494,3 +494,80 @@ def test_qsds_product_factors_vs_full_state(orc):
     assert np.max(np.abs(orc.factor_amplitudes(phi, zs) - psi)) < 1e-14
     _, e, _ = orc.observables(inst, psi)
     assert abs(orc.factor_energy(inst["h"], phi) - e) < 1e-13
+
+
+# ----------------------------------------------------------------------------- block-separable instances
+@pytest.mark.parametrize("p", [1, 3])
+@pytest.mark.parametrize("seed", [0, 1])
+def test_block_factorisation_vs_full_state(orc, p, seed):
+    """An instance whose couplings form disjoint cliques (used for sampled checks at
+    sizes no state vector fits): the tensor product of the components' QAOA states,
+    the summed energies, the product of the ground probabilities, the summed
+    gradients and the per-step observables against the oracle's full n = 12 state."""
+    n = 12
+    inst = I.block_instance(n, 900 + seed, block=4)
+    comps = orc.coupling_components(inst)
+    assert sorted(q for c in comps for q in c) == list(range(n)) and all(len(c) >= 2 for c in comps)
+    g, b = I.uniform_params(p, 910 + seed + p, -1.0, 1.0)
+    E = orc.energies(inst)
+    psi = orc.qaoa_state(inst, g, b, E=E)
+    blocks = orc.block_states(inst, g, b)
+    assert np.max(np.abs(orc.block_amplitudes(blocks, np.arange(1 << n)) - psi)) < 1e-14
+    _, en, pg = orc.observables(inst, psi, E=E)
+    ben, bpg = orc.block_observables(inst, blocks)
+    assert abs(ben - en) < 1e-12 * max(1.0, abs(en)) and abs(bpg - pg) < 1e-14
+    f, dg, db = orc.grad_tangent(inst, g, b, E=E)
+    bf, bdg, bdb = orc.block_grad(inst, g, b)
+    assert abs(bf - f) < 1e-12 and np.max(np.abs(bdg - dg)) < 1e-12 and np.max(np.abs(bdb - db)) < 1e-12
+    # per-step observables of a layer sequence
+    gs = orc.ground(inst, E)
+    st = orc.plus_state(n)
+    ens, pgs = orc.block_aqa_observables(inst, g, b)
+    for k in range(p):
+        st = orc.qaoa_state(inst, g[k:k + 1], b[k:k + 1], psi0=st, E=E)
+        _, e_k, p_k = orc.observables(inst, st, E=E, gs=gs)
+        assert abs(ens[k] - e_k) < 1e-12 * max(1.0, abs(e_k)) and abs(pgs[k] - p_k) < 1e-14
+
+
+def test_block_components_of_generator(orc):
+    """The block generator's coupling graph has the stated components at full size."""
+    for n, blk in ((32, 5), (33, 5), (34, 5)):
+        inst = I.block_instance(n, 40 + n, block=blk)
+        comps = orc.coupling_components(inst)
+        assert sorted(len(c) for c in comps) == sorted([blk] * (n // blk) + ([n % blk] if n % blk else []))
+        # the components scatter over the bit positions: some hold a low and a high qubit
+        assert sum(1 for c in comps if min(c) < 13 and max(c) >= 23) >= 2
+
+
+@pytest.mark.parametrize("p", [8])
+def test_gradient_tangent_p8_vs_dense_fd(orc, p):
+    """Forward-mode tangents at p = 8 (16 parameters, the depth of the gradient
+    workload) against central differences of the dense-matrix energy (Kronecker
+    products and scipy expm, no bit loops), Richardson pair h, h/2."""
+    n = 6
+    inst = I.degree4_int2(n, 77)
+    g, b = I.linear_ramp_params(p)
+    f, dg, db = orc.grad_tangent(inst, g, b)
+    HC, HD = dense.h_cost(inst), dense.h_driver(n)
+    from scipy.linalg import expm
+
+    def energy(gg, bb):
+        psi = dense.plus(n)
+        for x, y in zip(gg, bb):
+            psi = expm(-1j * y * HD) @ (expm(-1j * x * HC) @ psi)
+        return float(np.real(np.conj(psi) @ (HC @ psi)))
+
+    assert abs(f - energy(g, b)) < 1e-12
+
+    def central(k, is_gamma, h):
+        g1, b1, g2, b2 = g.copy(), b.copy(), g.copy(), b.copy()
+        (g1 if is_gamma else b1)[k] += h
+        (g2 if is_gamma else b2)[k] -= h
+        return (energy(g1, b1) - energy(g2, b2)) / (2 * h)
+
+    h = 1e-3
+    fg = np.array([(4 * central(k, True, h / 2) - central(k, True, h)) / 3 for k in range(p)])
+    fb = np.array([(4 * central(k, False, h / 2) - central(k, False, h)) / 3 for k in range(p)])
+    scale = max(1.0, orc.coeff_scale(inst))
+    assert np.max(np.abs(dg - fg)) < 1e-8 * scale
+    assert np.max(np.abs(db - fb)) < 1e-8 * scale
