@@ -154,6 +154,30 @@ int sv_qaoa_forward(sv_state s, sv_ising H, int p, const double* gamma, const do
 int sv_qaoa_energy(sv_state s, sv_ising H, int p, const double* gamma, const double* beta, int from_plus,
                    double* energy, double* p_gs, double* norm);
 
+/* sv_qaoa_energy for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same program, kernels and results as sv_qaoa_energy, but:
+ *   - d_out: caller-owned DEVICE array of 3 doubles, written on the state's
+ *     stream as (norm, energy, p_gs); the call returns after enqueueing and
+ *     does not synchronise (read d_out after the stream has completed);
+ *   - the reduction partials and phase tables live in a fixed 32 MiB device
+ *     array of the library (one per GPU, held until the process ends); the
+ *     call makes no hipMalloc / hipFree / pinned-host allocation;
+ *   - limits: partials of at most 2^20 tiles (every n up to 33 complex128 and
+ *     34 complex64) and phase tables of at most 2^19 entries (about
+ *     p * (33 + 2L) with L the integer-energy table half width: p = 4 at
+ *     L = 341 uses 3 k); beyond them SV_ERR_UNSUPPORTED, nothing enqueued;
+ *   - the instance must already hold its device tables for this n and dtype
+ *     and its ground-state cache: run sv_qaoa_energy once with a state of the
+ *     same n and dtype (or sv_ground and such a call) before; otherwise
+ *     SV_ERR_UNSUPPORTED, nothing enqueued;
+ *   - the state's device must be the current device (else SV_ERR_ARG).
+ * Every call on one GPU shares that GPU's array: calls that overlap on one
+ * GPU (different streams or host threads) race and must be serialised by the
+ * caller.  d_out NULL or not 8-byte aligned: SV_ERR_ARG. */
+int sv_qaoa_energy_noalloc(sv_state s, sv_ising H, int p, const double* gamma, const double* beta, int from_plus,
+                           double* d_out);
+
 /* Approximate quantum annealing (Sec. III.B.2): the same circuit, from |+>^n,
  * with `steps` (gamma_k, beta_k) pairs built by one of the schedule helpers
  * below.  If pgs_per_step / energy_per_step are non-NULL they receive, after

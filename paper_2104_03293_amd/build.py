@@ -39,7 +39,7 @@ def _compile(src: Path, obj: Path, verbose: bool) -> None:
 def build(verbose: bool = False) -> Path:
     objdir = HERE / "_build"
     objdir.mkdir(exist_ok=True)
-    srcs = [CSRC / "sv_kernels.hip", CSRC / "sv_api.cpp"]
+    srcs = [CSRC / "sv_kernels.hip", CSRC / "sv_api.cpp", CSRC / "sv_noalloc.hip"]
     objs = [objdir / (s.stem + ".o") for s in srcs]
     with ThreadPoolExecutor(max_workers=len(srcs)) as ex:
         list(ex.map(lambda so: _compile(so[0], so[1], verbose), zip(srcs, objs)))

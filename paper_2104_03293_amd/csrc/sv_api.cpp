@@ -664,7 +664,8 @@ static int build_geobuf(const Geometry& geo, const sv_ising_s* H, sv_dtype dt, G
 static std::mutex g_geo_mu;
 static std::map<GeoKey, GeoBuf*> g_plain_geos;  // instance-free tables (mixer-only passes)
 
-static int get_geobuf(const Geometry& geo, sv_ising_s* H, sv_dtype dt, GeoBuf** out) {
+// lookup_only: return the cached table or fail (calls that may not allocate).
+static int get_geobuf(const Geometry& geo, sv_ising_s* H, sv_dtype dt, GeoBuf** out, bool lookup_only = false) {
     uint64_t sig = 1469598103934665603ull;  // FNV-1a over the layout description
     auto mix = [&](uint64_t v) { sig = (sig ^ v) * 1099511628211ull; };
     for (size_t j = 0; j < geo.blocks.size(); j++) {
@@ -681,6 +682,10 @@ static int get_geobuf(const Geometry& geo, sv_ising_s* H, sv_dtype dt, GeoBuf** 
             *out = it->second;
             return SV_OK;
         }
+        if (lookup_only)
+            return fail(SV_ERR_UNSUPPORTED,
+                        "the instance has no device tables for this n, dtype and plan yet (run sv_qaoa_energy "
+                        "once with a state of the same n and dtype to build them)");
         int rc = build_geobuf(geo, H, dt, out);
         if (rc) return rc;
         H->geos[key] = *out;
@@ -692,6 +697,7 @@ static int get_geobuf(const Geometry& geo, sv_ising_s* H, sv_dtype dt, GeoBuf** 
         *out = it->second;
         return SV_OK;
     }
+    if (lookup_only) return fail(SV_ERR_UNSUPPORTED, "no geometry table for this n, dtype and plan yet");
     int rc = build_geobuf(geo, nullptr, dt, out);
     if (rc) return rc;
     g_plain_geos[key] = *out;
@@ -976,7 +982,8 @@ static IsingDev ising_dev(const sv_ising_s* H) {
 // Per-tile field table of an instance for a tile geometry, built once (on the
 // caller's stream, which is synchronized so that later passes on any stream
 // may use it) and kept until the instance is freed.
-static int get_tf(sv_ising_s* H, const Geometry& geo, const GeoBuf* gb, hipStream_t stream, const double** out) {
+static int get_tf(sv_ising_s* H, const Geometry& geo, const GeoBuf* gb, hipStream_t stream, const double** out,
+                  bool lookup_only = false) {
     const auto key = std::make_tuple(geo.T, geo.c, geo.lo, geo.g, geo.n);
     std::lock_guard<std::mutex> g(H->mu);
     auto it = H->tfs.find(key);
@@ -984,6 +991,10 @@ static int get_tf(sv_ising_s* H, const Geometry& geo, const GeoBuf* gb, hipStrea
         *out = it->second;
         return SV_OK;
     }
+    if (lookup_only)
+        return fail(SV_ERR_UNSUPPORTED,
+                    "the instance has no field table for this n, dtype and plan yet (run sv_qaoa_energy once with "
+                    "a state of the same n and dtype to build it)");
     double* d = nullptr;
     HIPCHECK(hipMalloc(&d, geo.ntiles * (size_t)kTF * sizeof(double)));
     TfArgs a;
@@ -1028,22 +1039,48 @@ static Plan make_plan(int n, sv_dtype dt, bool grad = false, bool general = fals
     return pl;
 }
 
+// fx != nullptr: the call may not allocate.  Partials and phase tables go to the
+// fixed device region fx describes, every result is written once, straight to
+// fx->out (no clearing), and the instance's tables and ground-state cache must
+// already exist; programs that need more (spin sums, general layers) are refused.
 static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& prog, const Plan& plan,
-                       bool need_ground) {
+                       bool need_ground, const FixedScratch* fx = nullptr) {
     finalize_program(prog, plan.by_nv);
     if (s->failed) return fail(SV_ERR_HIP, "state is in a failed state after an earlier HIP error");
     double emin = 0.0, etol = 0.0;
     if (need_ground && H) {
-        int rc = run_ground(H, s->stream);
-        if (rc) return rc;
+        if (fx) {
+            std::lock_guard<std::mutex> g(H->mu);
+            if (!H->has_ground)
+                return fail(SV_ERR_UNSUPPORTED, "the instance has no ground-state cache yet (call sv_ground once)");
+        } else {
+            int rc = run_ground(H, s->stream);
+            if (rc) return rc;
+        }
         emin = H->emin;
         etol = ground_tol(H);
     }
     size_t part_need = 1;
     for (const Pass& p : prog.passes)
         part_need = std::max(part_need, (size_t)plan.by_nv[p.nv][p.group].ntiles * std::max<size_t>(1, p.slot_dst.size()));
-    int rc = ensure_work(s, part_need, std::max(prog.nres, 1));
-    if (rc) return rc;
+    int rc = SV_OK;
+    if (fx) {
+        if (part_need > fx->part_doubles)
+            return fail(SV_ERR_UNSUPPORTED, "reduction partials need %zu doubles, the fixed scratch holds %zu",
+                        part_need, fx->part_doubles);
+        std::vector<int> writers(std::max(prog.nres, 0), 0);
+        for (const Pass& p : prog.passes) {
+            if (p.spin_res >= 0) return fail(SV_ERR_UNSUPPORTED, "spin sums need allocated scratch");
+            for (int d : p.slot_dst)
+                if (d >= 0 && d < prog.nres) writers[d]++;
+        }
+        for (int w : writers)
+            if (w != 1) return fail(SV_ERR_UNSUPPORTED, "internal: a result without exactly one writer");
+    } else {
+        rc = ensure_work(s, part_need, std::max(prog.nres, 1));
+        if (rc) return rc;
+    }
+    double* const d_part = fx ? fx->part : s->w.d_part;
     size_t spin_need = 0;
     for (const Pass& p : prog.passes)
         if (p.spin_res >= 0) spin_need = std::max(spin_need, (size_t)plan.by_nv[p.nv][p.group].ntiles * kTF);
@@ -1054,7 +1091,7 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         HIPCHECK(hipMalloc(&s->w.d_spin, spin_need * sizeof(double)));
         s->w.spin_cap = spin_need;
     }
-    if (prog.nres > 0) {
+    if (prog.nres > 0 && !fx) {
         hipError_t e = hipMemsetAsync(s->w.d_res, 0, prog.nres * sizeof(double), s->stream);
         if (e != hipSuccess) {
             s->failed = true;
@@ -1072,7 +1109,7 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         if (p.phase.empty()) continue;
         const Geometry& geo = plan.by_nv[p.nv][p.group];
         GeoBuf* gb = nullptr;
-        rc = get_geobuf(geo, H, s->dt, &gb);
+        rc = get_geobuf(geo, H, s->dt, &gb, fx != nullptr);
         if (rc) return rc;
         for (const auto& ph : p.phase) {
             TableJob j{};
@@ -1089,15 +1126,19 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
             jobs.push_back(j);
         }
     }
-    if (tab_need > s->w.tab_cap) {
+    if (fx && tab_need > fx->tab_entries)
+        return fail(SV_ERR_UNSUPPORTED, "phase tables need %zu entries, the fixed scratch holds %zu", tab_need,
+                    fx->tab_entries);
+    if (!fx && tab_need > s->w.tab_cap) {
         if (s->w.d_tab) (void)hipFree(s->w.d_tab);
         s->w.d_tab = nullptr;
         s->w.tab_cap = 0;
         HIPCHECK(hipMalloc(&s->w.d_tab, tab_need * sizeof(double2)));
         s->w.tab_cap = tab_need;
     }
+    double2* const d_tab = fx ? fx->tab : s->w.d_tab;
     if (!jobs.empty()) {
-        int e = launch_tables(jobs.data(), (int)jobs.size(), s->w.d_tab, s->stream);
+        int e = launch_tables(jobs.data(), (int)jobs.size(), d_tab, s->stream);
         if (e != 0) {
             s->failed = true;
             return fail(SV_ERR_HIP, "table launch failed: %s", hipGetErrorString((hipError_t)e));
@@ -1116,6 +1157,7 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         }
     }
     if (nblk > 0) {
+        if (fx) return fail(SV_ERR_UNSUPPORTED, "general layers need allocated scratch");
         if (!prog.layers || prog.nq != s->n) return fail(SV_ERR_ARG, "internal: general layers without matrices");
         const size_t need = nblk * (size_t)kGenBlock;
         // the staging buffer may still feed the previous call's copy
@@ -1166,13 +1208,13 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         const Geometry& geo = plan.by_nv[p.nv][p.group];
         if (p.nv == 2 && !lam) return fail(SV_ERR_ARG, "internal: two-vector pass without lam");
         GeoBuf* gb = nullptr;
-        rc = get_geobuf(geo, H, s->dt, &gb);
+        rc = get_geobuf(geo, H, s->dt, &gb, fx != nullptr);
         if (rc) return rc;
         PassArgs a;
         memset(&a, 0, sizeof(a));
         a.psi = s->ptr;
         a.lam = lam ? lam->ptr : nullptr;
-        a.partials = s->w.d_part;
+        a.partials = d_part;
         a.geo = gb;
         a.ntiles = geo.ntiles;
         a.n = s->n;
@@ -1197,11 +1239,11 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         }
         a.tf = nullptr;
         if (a.need_e) {
-            rc = get_tf(H, geo, gb, s->stream, &a.tf);
+            rc = get_tf(H, geo, gb, s->stream, &a.tf, fx != nullptr);
             if (rc) return rc;
         }
         a.nphase = (int)p.phase.size();
-        a.ptab = s->w.d_tab;
+        a.ptab = d_tab;
         a.lut_half = lut_half;
         a.lut_q = H && H->qden > 0 ? (double)H->qden : 1.0;
         a.spin_part = p.spin_res >= 0 ? s->w.d_spin : nullptr;
@@ -1228,7 +1270,7 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         for (int i = 0; i < kMaxOps; i++)
             if (genblk[pi][i] >= 0 && !genreal[pi][i]) a.gen_real = 0;
         hipEvent_t ev0;
-        const bool prof = prof_begin(s->stream, &ev0);
+        const bool prof = !fx && prof_begin(s->stream, &ev0);
         int e = take_injected_failure() ? (int)hipErrorLaunchFailure : launch_pass((int)s->dt, p.nv, geo.T, a, s->stream);
         if (prof) {
             const int nrd = (p.load & 4) ? 0 : __builtin_popcount(p.load & 3);
@@ -1260,8 +1302,8 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
             }
         }
         if (a.nslots > 0) {
-            e = launch_reduce_slots(s->w.d_part, geo.ntiles, a.nslots, p.slot_dst.data(), 1, s->w.d_res,
-                                    s->stream);
+            e = launch_reduce_slots(d_part, geo.ntiles, a.nslots, p.slot_dst.data(), fx ? 0 : 1,
+                                    fx ? fx->out : s->w.d_res, s->stream);
             if (e != 0) {
                 s->failed = true;
                 return fail(SV_ERR_HIP, "reduce launch failed: %s", hipGetErrorString((hipError_t)e));
@@ -1716,6 +1758,34 @@ extern "C" int sv_qaoa_forward(sv_state s, sv_ising H, int p, const double* gamm
     return run_program(s, nullptr, H, prog, plan, false);
 }
 
+// Program of one energy evaluation: the forward circuit with the reduction
+// (results 0..2: norm, energy, p_gs) merged into its last mixer pass.
+static Program energy_program(const sv_state_s* s, const Plan& plan, int p, const double* gamma, const double* beta,
+                              int from_plus) {
+    std::vector<Event> ev;
+    forward_events(ev, group_order((int)plan.by_nv[1].size(), (int)s->dt, s->n), p, gamma, beta, from_plus != 0, -1);
+    Event r{EV_REDUCE};
+    r.res = 0;
+    ev.push_back(r);  // merges into the last mixer pass as its point op
+    return build_program(ev, 3, knob_for("fuse", (int)s->dt, s->n) != 0);
+}
+
+int sv_internal_set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+
+int sv_internal_qaoa_energy_fixed(sv_state s, sv_ising H, int p, const double* gamma, const double* beta,
+                                  int from_plus, int device, const FixedScratch& fx) {
+    int rc = check_pair(s, H, "sv_qaoa_energy_noalloc");
+    if (rc) return rc;
+    rc = check_angles(p, gamma, beta, "sv_qaoa_energy_noalloc");
+    if (rc) return rc;
+    if (s->device != device)
+        return fail(SV_ERR_ARG, "sv_qaoa_energy_noalloc: the state lives on device %d, device %d is current", s->device,
+                    device);
+    Plan plan = make_plan(s->n, s->dt);
+    Program prog = energy_program(s, plan, p, gamma, beta, from_plus);
+    return run_program(s, nullptr, H, prog, plan, true, &fx);
+}
+
 extern "C" int sv_qaoa_energy(sv_state s, sv_ising H, int p, const double* gamma, const double* beta,
                               int from_plus, double* energy, double* p_gs, double* norm) {
     int rc = check_pair(s, H, "sv_qaoa_energy");
@@ -1723,12 +1793,7 @@ extern "C" int sv_qaoa_energy(sv_state s, sv_ising H, int p, const double* gamma
     rc = check_angles(p, gamma, beta, "sv_qaoa_energy");
     if (rc) return rc;
     Plan plan = make_plan(s->n, s->dt);
-    std::vector<Event> ev;
-    forward_events(ev, group_order((int)plan.by_nv[1].size(), (int)s->dt, s->n), p, gamma, beta, from_plus != 0, -1);
-    Event r{EV_REDUCE};
-    r.res = 0;
-    ev.push_back(r);  // merges into the last mixer pass as its point op
-    Program prog = build_program(ev, 3, knob_for("fuse", (int)s->dt, s->n) != 0);
+    Program prog = energy_program(s, plan, p, gamma, beta, from_plus);
     rc = run_program(s, nullptr, H, prog, plan, true);
     if (rc) return rc;
     rc = fetch_results(s, 3);

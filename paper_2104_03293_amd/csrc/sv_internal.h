@@ -19,7 +19,10 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
+
+#include "sv.h"
 
 namespace svk {
 
@@ -241,6 +244,18 @@ int launch_batch_scan(int dtype, const BatchArgs& a, int grid, int wide, void* s
 int batch_lds_bits(int dtype, int wide);  // log2 of the LDS-resident state of a batch variant
 int batch_lut_cap(int dtype, int wide);   // phase-table entries of a batch variant
 
+// ---------------------------------------------------------------- fixed scratch
+// Device region that a call which may not allocate uses instead of the state's
+// work buffers: reduction partials, phase tables and the result array.
+struct FixedScratch {
+    double* part;           // reduction partials
+    size_t part_doubles;
+    double2* tab;           // phase tables
+    size_t tab_entries;     // double2 entries
+    double* out;            // results (device), each written by exactly one reduction
+};
+
+
 // Compile-time tile shapes per (dtype, vectors): T tile bits, R register bits.
 struct Shape {
     int T, R;
@@ -248,3 +263,13 @@ struct Shape {
 Shape shape_for(int dtype, int nv, bool grad);
 
 }  // namespace svk
+
+// Host entry points shared between the C-ABI source files (sv_api.cpp).
+// sv_qaoa_energy on a fixed scratch region: the same program and kernels,
+// results (norm, energy, p_gs) written to fx.out on the state's stream, nothing
+// allocated, no synchronisation.  device: the current HIP device, which must be
+// the state's.
+int sv_internal_qaoa_energy_fixed(sv_state s, sv_ising H, int p, const double* gamma, const double* beta,
+                                  int from_plus, int device, const svk::FixedScratch& fx);
+// Set the thread-local message of sv_last_error; returns code.
+int sv_internal_set_error(int code, const char* msg);

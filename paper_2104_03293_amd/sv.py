@@ -58,6 +58,7 @@ def _load():
         "sv_mixer": (ip, [vp, ctypes.c_double]),
         "sv_qaoa_forward": (ip, [vp, vp, ip, dp, dp, ip]),
         "sv_qaoa_energy": (ip, [vp, vp, ip, dp, dp, ip, dp, dp, dp]),
+        "sv_qaoa_energy_noalloc": (ip, [vp, vp, ip, dp, dp, ip, vp]),
         "sv_aqa_run": (ip, [vp, vp, ip, dp, dp, dp, dp]),
         "sv_aqa_run_observe": (ip, [vp, vp, ip, dp, dp, dp, dp, dp]),
         "sv_spin_z": (ip, [vp, dp]),
@@ -276,6 +277,22 @@ def qaoa_energy(s: State, H: Ising, gamma, beta, from_plus: bool = True):
     _check(lib.sv_qaoa_energy(s.handle, H.handle, len(g), _dp(g), _dp(b), int(bool(from_plus)), ctypes.byref(e),
                               ctypes.byref(p), ctypes.byref(n)))
     return e.value, p.value, n.value
+
+
+def qaoa_energy_noalloc(s: State, H: Ising, gamma, beta, out, from_plus: bool = True) -> None:
+    """sv_qaoa_energy without allocation: writes (norm, energy, p_gs) into the
+    float64 CUDA tensor out (3 elements, on the state's device) on the state's
+    stream and returns without synchronising."""
+    import torch
+
+    g, b = _f64(gamma), _f64(beta)
+    if len(g) != len(b):
+        raise ValueError("gamma and beta must have equal length")
+    if not (isinstance(out, torch.Tensor) and out.is_cuda and out.dtype == torch.float64 and out.numel() >= 3
+            and out.is_contiguous()):
+        raise ValueError("out must be a contiguous float64 CUDA tensor of at least 3 elements")
+    _check(lib.sv_qaoa_energy_noalloc(s.handle, H.handle, len(g), _dp(g), _dp(b), int(bool(from_plus)),
+                                      ctypes.c_void_p(out.data_ptr())))
 
 
 def aqa_run(s: State, H: Ising, gamma, beta, per_step: bool = False):
