@@ -139,6 +139,16 @@ def main():
     roof["passes_per_layer"] = round(k["launches"] / args.steps / p, 3)
     roof["one_pass_floor_frac"] = round(2 * state_bytes / (HBM_PEAK_GBS * 1e9) / t_layer, 4)
     roof["gate_sweeps_per_layer"] = 2 * n + len(inst["J"])
+    # per tile geometry: T tile bits, c carrier bits (runs of 2^c amplitudes), L layouts, w write-only
+    by_geo = {}
+    for key, rec in sorted(prof.items()):
+        if not key.startswith(kind + "/"):
+            continue
+        g_ms = rec["ms"] / max(1, rec["launches"])
+        by_geo[key.split("/", 1)[1]] = {"launches_per_step": rec["launches"] / args.steps, "avg_ms": round(g_ms, 4),
+                                        "GBps": round(rec["bytes"] / (rec["ms"] * 1e-3) / 1e9, 1)}
+        log(f"[bench]   {key}: {by_geo[key.split('/', 1)[1]]}")
+    roof["by_geometry"] = by_geo
     log(f"[bench] k_pass {achieved:.0f} GB/s; device copy {copy_gbs:.0f} GB/s")
 
     extras = {}

@@ -54,7 +54,8 @@ std::map<std::string, int> g_knobs = {
     {"ntmin", 4},     // passes whose contiguous runs hold >= 2^ntmin amplitudes stream with nontemporal hints
     {"persist", 0},   // tile passes: workgroups per CU of a persistent grid (0: one workgroup per tile)
     {"stagger", 0},   // persistent grids: start delay of the second half (units of 64*127 clocks)
-    {"snake", 1},     // 1: the contiguous tile group takes a middle slot of the layer's group order
+    {"snake", 1},     // group order of a layer: 1 = B, A, C, ... (the contiguous group A in a middle slot);
+                      // 2 = last group first (C, A, B, ...); 0 = A, B, C, ...
     {"dpp", 1},       // 1: one active bit may be butterflied across lanes to save a layout
     {"ldsswz", 4},    // LDS slot swizzle width of the tile passes (3..5)
     {"batchwide", 2}, // complex64 batch scan: 2 = 2^13 LDS states, four waves, two workgroups
@@ -68,7 +69,20 @@ std::map<std::string, int> g_knobs = {
     {"c64g14", 2},    // complex64 adjoint programs on 14-bit tiles: 1 always, 2 when fewer groups, 0 never
     {"ntinit", 1},    // write-only first passes: 1 = nontemporal stores
     {"split", 0},     // bits above the contiguous tile: 0 = near-equal groups, 1 = largest groups first
+    {"xcd", -1},      // x > 0: XCD-aware tile order, 8 * 2^(x-1) interleaved streams of contiguous tiles;
+                      // 0: tile = workgroup index; -1: 8 streams for states up to 64 GiB, 32 above
+                      // (n = 32 complex128: 241 -> 226 ms per p = 4 evaluation; n = 33: 589 -> 461 ms)
+    {"c128t14", 0},   // complex128 one-vector programs (not the adjoint): 1 = 14-bit tiles (512 threads,
+                      // one workgroup per CU), 0 = 13-bit tiles (256 threads, two workgroups per CU)
     {"fail_next_launch", 0},  // 1: the next tile-pass launch reports a launch failure (error-path tests)
+};
+// Accepted range of every knob.
+const std::map<std::string, std::pair<int, int>> g_knob_range = {
+    {"fuse", {0, 1}},    {"cmin64", {0, 8}},   {"cmin128", {0, 8}},  {"ntmin", {0, 64}},   {"persist", {0, 8}},
+    {"stagger", {0, 64}}, {"snake", {0, 2}},   {"dpp", {0, 1}},      {"ldsswz", {3, 5}},   {"batchwide", {0, 2}},
+    {"batch128", {0, 1}}, {"c64t13", {0, 1}},  {"c64occ", {0, 1}},   {"c64g4", {0, 1}},    {"kc34", {0, 1}},
+    {"c64g14", {0, 2}},  {"ntinit", {0, 1}},   {"split", {0, 1}},    {"xcd", {-1, 5}},      {"c128t14", {0, 1}},
+    {"fail_next_launch", {0, 1}},
 };
 int knob(const char* k) {
     std::lock_guard<std::mutex> g(g_knob_mu);
@@ -139,25 +153,9 @@ extern "C" int sv_tune_set(const char* name, int value) {
     std::lock_guard<std::mutex> g(g_knob_mu);
     auto it = g_knobs.find(name);
     if (it == g_knobs.end()) return fail(SV_ERR_ARG, "sv_tune_set: unknown knob '%s'", name);
-    if (std::string(name) == "fuse" && (value < 0 || value > 1)) return fail(SV_ERR_ARG, "fuse must be 0 or 1");
-    if ((std::string(name) == "cmin64" || std::string(name) == "cmin128") && (value < 0 || value > 8))
-        return fail(SV_ERR_ARG, "%s must be in [0, 8]", name);
-    if (std::string(name) == "ntmin" && (value < 0 || value > 64)) return fail(SV_ERR_ARG, "ntmin must be in [0, 64]");
-    if (std::string(name) == "persist" && (value < 0 || value > 8)) return fail(SV_ERR_ARG, "persist must be in [0, 8]");
-    if (std::string(name) == "ldsswz" && (value < 3 || value > 5)) return fail(SV_ERR_ARG, "ldsswz must be in [3, 5]");
-    if ((std::string(name) == "snake" || std::string(name) == "dpp" || std::string(name) == "c64t13" ||
-         std::string(name) == "c64occ" || std::string(name) == "c64g4" || std::string(name) == "kc34" ||
-         std::string(name) == "ntinit") &&
-        (value < 0 || value > 1))
-        return fail(SV_ERR_ARG, "%s must be 0 or 1", name);
-    if ((std::string(name) == "split" || std::string(name) == "fail_next_launch") && (value < 0 || value > 1))
-        return fail(SV_ERR_ARG, "%s must be 0 or 1", name);
-    if (std::string(name) == "c64g14" && (value < 0 || value > 2)) return fail(SV_ERR_ARG, "c64g14 must be in [0, 2]");
-    if (std::string(name) == "batchwide" && (value < 0 || value > 2))
-        return fail(SV_ERR_ARG, "batchwide must be in [0, 2]");
-    if (std::string(name) == "batch128" && (value < 0 || value > 1))
-        return fail(SV_ERR_ARG, "batch128 must be 0 or 1");
-    if (std::string(name) == "stagger" && (value < 0 || value > 64)) return fail(SV_ERR_ARG, "stagger must be in [0, 64]");
+    const auto& rg = g_knob_range.at(name);
+    if (value < rg.first || value > rg.second)
+        return fail(SV_ERR_ARG, "%s must be in [%d, %d]", name, rg.first, rg.second);
     it->second = value;
     return SV_OK;
 }
@@ -210,10 +208,15 @@ extern "C" int sv_profile_report(char* buf, size_t len) {
         float ms = 0.f;
         e = hipEventElapsedTime(&ms, r.a, r.b);
         if (e != hipSuccess) return fail(SV_ERR_HIP, "profile: %s", hipGetErrorString(e));
-        auto& t = agg[r.kind];
-        std::get<0>(t) += 1;
-        std::get<1>(t) += ms;
-        std::get<2>(t) += r.bytes;
+        // "kind/detail" records count under the kind and under the full name
+        const size_t slash = r.kind.find('/');
+        for (const std::string& key : {r.kind.substr(0, slash), r.kind}) {
+            auto& t = agg[key];
+            std::get<0>(t) += 1;
+            std::get<1>(t) += ms;
+            std::get<2>(t) += r.bytes;
+            if (slash == std::string::npos) break;
+        }
     }
     std::string js = "{";
     bool first = true;
@@ -526,7 +529,7 @@ static Geometry make_geometry(int n, int T, int R, int c, int lo, int g, int G, 
 // Tile groups covering all qubits: group A = tile bits 0..T-1 (contiguous),
 // then the bits above T split into near-equal groups of at most T - cmin bits,
 // each tile carrying 2^c contiguous amplitudes (c = T - g >= cmin).
-static std::vector<Geometry> plan_groups(int n, sv_dtype dt, int nv, bool grad = false) {
+static std::vector<Geometry> plan_groups(int n, sv_dtype dt, int nv, bool grad = false, bool general = false) {
     Shape sh = shape_for((int)dt, nv, grad);
     // complex64 adjoint family on 14-bit tiles: the forward tiles, and 1024-thread two-vector
     // tiles of 4 register bits.  Knob c64g14: 1 always, 2 (default) when that needs fewer tile
@@ -537,6 +540,8 @@ static std::vector<Geometry> plan_groups(int n, sv_dtype dt, int nv, bool grad =
         auto ngroups = [&](int T) { return n <= T ? 1 : 1 + (n - T + (T - cm) - 1) / (T - cm); };
         if (mode == 1 || (mode == 2 && ngroups(14) < ngroups(13))) sh = nv == 1 ? Shape{14, 5} : Shape{14, 4};
     }
+    // complex128 one-vector programs on 14-bit tiles (general single-qubit layers keep 13-bit tiles)
+    if (dt == SV_C128 && nv == 1 && !grad && !general && knob_for("c128t14", (int)dt, n) != 0) sh = Shape{14, 5};
     const int T = sh.T, R = sh.R, G = swz_bits(dt);
     // lane positions the one-vector kernels butterfly across lanes: 3, and 4 for
     // 14-bit complex64 tiles.  Two-vector passes keep every qubit in registers:
@@ -1034,8 +1039,8 @@ static Plan make_plan(int n, sv_dtype dt, bool grad = false, bool general = fals
     // complex64 one-vector programs may use the 13-bit tiles of the adjoint family
     // (not programs with general single-qubit layers, whose kernels exist for 14-bit tiles)
     if (dt == SV_C64 && !general && knob_for("c64t13", (int)dt, n) != 0) grad = true;
-    pl.by_nv[1] = plan_groups(n, dt, 1, grad);
-    pl.by_nv[2] = plan_groups(n, dt, 2, grad);
+    pl.by_nv[1] = plan_groups(n, dt, 1, grad, general);
+    pl.by_nv[2] = plan_groups(n, dt, 2, grad, general);
     return pl;
 }
 
@@ -1233,6 +1238,8 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         a.swz = lds_swz_bits(s->dt, s->n);
         a.grid = persist * ncu;
         a.stagger = stagger;
+        a.xcd = knob_for("xcd", (int)s->dt, s->n);
+        if (a.xcd < 0) a.xcd = ((size_t(1) << s->n) * elem_size(s->dt)) > (size_t(64) << 30) ? 3 : 1;
         for (const Op& op : p.ops) {
             a.nops += op.kind != 0;
             if (op.kind == OP_POINT && H) a.need_e = 1;
@@ -1275,8 +1282,11 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         if (prof) {
             const int nrd = (p.load & 4) ? 0 : __builtin_popcount(p.load & 3);
             const int nwr = __builtin_popcount(p.store & 3);
+            // kind/geometry: aggregated under the kind, and per tile shape, carrier bits and layouts
             const std::string kind = std::string("pass_") + (s->dt == SV_C128 ? "c128" : "c64") + "_nv" +
-                                     std::to_string(p.nv);
+                                     std::to_string(p.nv) + "/T" + std::to_string(geo.T) + "c" +
+                                     std::to_string(geo.c) + "L" + std::to_string(a.nlayouts) +
+                                     ((p.load & 4) ? "w" : "");
             prof_end(s->stream, ev0, kind, (double)(nrd + nwr) * (double)s->bytes);
         }
         if (e != 0) {
@@ -1693,8 +1703,14 @@ extern "C" int sv_cost_phase(sv_state s, sv_ising H, double gamma) {
 // contiguous group A streams fastest, so it takes a middle position.
 static std::vector<int> group_order(int ngroups, int dt, int n) {
     std::vector<int> o;
-    if (ngroups <= 2 || knob_for("snake", dt, n) == 0) {
+    const int mode = knob_for("snake", dt, n);
+    if (ngroups <= 2 || mode == 0) {
         for (int i = 0; i < ngroups; i++) o.push_back(i);
+        return o;
+    }
+    if (mode == 2) {  // the last (shortest-carrier-free) group first: C, A, B, ...
+        o.push_back(ngroups - 1);
+        for (int i = 0; i < ngroups - 1; i++) o.push_back(i);
         return o;
     }
     o.push_back(1);

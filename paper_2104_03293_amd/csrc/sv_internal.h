@@ -158,6 +158,9 @@ struct PassArgs {
     int32_t swz;            // LDS slot swizzle width (the geometry tables use the same)
     int32_t grid;           // workgroups launched (< ntiles: persistent grid-stride walk), 0: one per tile
     int32_t stagger;        // persistent grids: start delay of the second half, in units of s_sleep(127)
+    int32_t xcd;            // x > 0: with K = 8 * 2^(x-1), workgroup b takes tile (b mod K) * (ntiles / K)
+                            // + b / K, so that each of the 8 XCDs (which receive workgroups round-robin)
+                            // walks K / 8 contiguous stretches of the tiles; 0: tile = b
     int32_t nphase;
     int32_t lut_half;       // L of the phase tables (in units of 1/q), -1 for other real-valued instances
     double lut_q;           // q: table index = q * energy

@@ -438,6 +438,12 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
         for (int i = 0; i < a.stagger; i++) __builtin_amdgcn_s_sleep(127);
     }
     uint64_t tile = blockIdx.x;
+    if (!PERSIST && a.xcd > 0) {
+        // K = 8 * 2^(xcd - 1) interleaved streams: workgroup b walks stream b mod K
+        const int kb = 2 + a.xcd;
+        if ((a.ntiles & ((1ull << kb) - 1ull)) == 0 && gridDim.x == a.ntiles)
+            tile = (uint64_t)(blockIdx.x & ((1u << kb) - 1u)) * (a.ntiles >> kb) + (blockIdx.x >> kb);
+    }
     do {
         const uint64_t base = tg.base(tile);
 
@@ -1034,7 +1040,8 @@ static int run_pass(const PassArgs& a, void* stream) {
     const dim3 grid(nwg), block(1 << (T - R));
     hipStream_t st = (hipStream_t)stream;
     const bool fast = a.phantom == 0 && (a.lut_half >= 0 || a.nphase == 0);
-    if constexpr (NV == 1 && (sizeof(Real) == 8 || T == 14)) {
+    // general-layer kernels exist for 13-bit complex128 and 14-bit complex64 tiles
+    if constexpr (NV == 1 && ((sizeof(Real) == 8 && T == 13) || (sizeof(Real) == 4 && T == 14))) {
         if (a.gmat) {  // general single-qubit layers (real matrices: half the arithmetic)
             // general kernels need more registers than the four-waves-per-SIMD budget
             constexpr int GMB = MINB > 2 ? 2 : MINB;
@@ -1126,6 +1133,8 @@ int launch_pass(int dtype, int nv, int T, const PassArgs& a, void* stream) {
     if (nv == 2 && a.nslots > 4) return (int)hipErrorInvalidValue;
     if (a.nlayouts < 1 || a.nlayouts > kMaxLayouts) return (int)hipErrorInvalidValue;
     if (dtype == 2) {
+        // 14-bit complex128 tiles: 512 threads, one workgroup per CU (128 KiB half-tile exchanges)
+        if (nv == 1 && T == 14) return run_pass<double, 14, 5, 1, 8, 2>(a, stream);
         if (nv == 1) return run_pass<double, 13, 5, 1, 8, 2>(a, stream);
         return run_pass<double, 13, 4, 2, 4, 1>(a, stream);
     }

@@ -317,3 +317,41 @@ def test_block_instance_full_size_annealing(sv, orc, record_error, dtype, n):
     serr = float(np.max(np.abs(sz[-1] - ref_sz)))
     record_error(f"spin max-abs {dtype}", serr)
     assert serr <= PROB_TOL[dtype] * 10
+
+
+# ----------------------------------------------------------------------------- XCD-aware tile orders
+@pytest.mark.parametrize("dtype,n", [("c128", 26), ("c64", 26), ("c128", 15)])
+def test_xcd_tile_orders_agree(sv, orc, record_error, dtype, n):
+    """The XCD-aware tile orders only change which workgroup takes which tile;
+    the per-tile partial sums are indexed by tile, so the state, the observables
+    and the adjoint gradient are bit-identical for every order (knob xcd = 0 ..
+    5, and the automatic choice -1; at n = 15 the tile count is below the
+    stream count and the plain order is kept), and they match the oracle."""
+    inst = I.degree4_int2(n, 640 + n)
+    H = sv.Ising.from_instance(inst)
+    g, b = I.uniform_params(3, 641 + n, -1.1, 1.1)
+    out = {}
+    for x in (-1, 0, 1, 2, 3, 4, 5):
+        with Knob(sv, "xcd", x):
+            s = sv.State(n, dtype)
+            lam = sv.State(n, dtype)
+            e, pg, nrm = sv.qaoa_energy(s, H, g, b)
+            psi = s.to_numpy()
+            ge, dg, db = sv.grad(s, lam, H, g, b)
+            out[x] = (e, pg, nrm, psi, ge, dg, db)
+            del s, lam
+    ref = out[0]
+    for x, o in out.items():
+        assert o[:3] == ref[:3], (x, o[:3], ref[:3])
+        assert np.array_equal(o[3], ref[3]), x
+        assert o[4] == ref[4] and np.array_equal(o[5], ref[5]) and np.array_equal(o[6], ref[6]), x
+    E = orc.energies(inst)
+    rpsi = orc.qaoa_state(inst, g, b, E=E)
+    err = float(np.max(np.abs(ref[3] - rpsi)))
+    record_error(f"amp max-abs {dtype}", err)
+    assert err <= AMP_TOL[dtype]
+    _, rg, rb = orc.grad_tangent(inst, g, b)
+    scale = grad_scale(orc, inst, rg, rb)
+    gerr = max(np.max(np.abs(ref[5] - rg)), np.max(np.abs(ref[6] - rb))) / scale
+    record_error(f"grad / scale {dtype}", gerr)
+    assert gerr <= GRAD_TOL[dtype]
