@@ -44,10 +44,10 @@ def main():
     ap.add_argument("--dtype", default="c128")
     ap.add_argument("--no-extras", action="store_true", help="skip gradient / c64 / CPU-baseline legs")
     ap.add_argument("--extras", default="all",
-                    help="comma list of extra legs: grad,c64,exact_cover,hadamard,qsds,batch_scan,optimizer,cpu "
+                    help="comma list of extra legs: grad,c64,exact_cover,hadamard,qsds,batch_scan,optimizer,full,cpu "
                          "(default all)")
     ap.add_argument("--cpu-sample-n", type=int, default=28)
-    ap.add_argument("--cpu-sample-p", type=int, default=8)
+    ap.add_argument("--cpu-sample-p", type=int, default=4)
     ap.add_argument("--knob", action="append", default=[], metavar="NAME=VALUE",
                     help="set a plan knob of the library before the run (repeatable)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
@@ -113,19 +113,10 @@ def main():
     avg_bytes = k["bytes"] / max(1, k["launches"])
     achieved = avg_bytes / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     traffic = committed_traffic(args.dtype, n, p)
-    # measured ceiling: a plain device-to-device copy of 4 GiB (read + write)
-    src = torch.empty(1 << 29, dtype=torch.float64, device="cuda")
-    src.fill_(1.0)
-    dst = torch.empty_like(src)
-    dst.copy_(src)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(5):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    copy_gbs = 5 * 2 * src.numel() * 8 / (e0.elapsed_time(e1) * 1e-3) / 1e9
-    del src, dst
+    # measured ceilings: the library's streaming kernel (in-place nontemporal read + write of the
+    # state, no arithmetic) with the tile shape and tile order of each pass geometry of the plan
+    ceil = stream_ceilings(sv, s, n, args.dtype)
+    copy_gbs = ceil[f"c{ceil['T']}"]
     roof = {"bound": "hbm", "kernel": f"k_pass<{args.dtype}>", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
             "launches_per_step": k["launches"] / args.steps, "avg_launch_ms": round(avg_ms, 4),
@@ -149,11 +140,22 @@ def main():
                                         "GBps": round(rec["bytes"] / (rec["ms"] * 1e-3) / 1e9, 1)}
         log(f"[bench]   {key}: {by_geo[key.split('/', 1)[1]]}")
     roof["by_geometry"] = by_geo
-    log(f"[bench] k_pass {achieved:.0f} GB/s; device copy {copy_gbs:.0f} GB/s")
+    # streaming-ceiling time of the same passes (each pass's bytes at its geometry's ceiling)
+    t_ceil = 0.0
+    for gk, rec in by_geo.items():
+        c_key = gk[gk.index("c"):gk.index("L")]
+        rate = ceil.get(c_key)
+        if rate:
+            t_ceil += rec["GBps"] * rec["avg_ms"] * rec["launches_per_step"] / rate
+    roof["stream_ceilings"] = {k: v for k, v in ceil.items() if k != "T"}
+    pass_ms = sum(r["avg_ms"] * r["launches_per_step"] for r in by_geo.values())
+    roof["frac_of_ceiling"] = round(t_ceil / pass_ms, 4) if pass_ms > 0 else None
+    log(f"[bench] k_pass {achieved:.0f} GB/s; streaming ceilings {roof['stream_ceilings']}")
 
     extras = {}
     legs = set() if args.no_extras else (
-        {"grad", "c64", "exact_cover", "hadamard", "qsds", "batch_scan", "optimizer", "cpu"} if args.extras == "all"
+        {"grad", "c64", "exact_cover", "hadamard", "qsds", "batch_scan", "optimizer", "full", "cpu"}
+        if args.extras == "all"
         else set(args.extras.split(",")))
     if "grad" in legs:
         # adjoint gradient vs finite differences (2p + 1 forward evaluations)
@@ -296,6 +298,16 @@ def main():
         dev.close()
         del Ho
 
+    if "full" in legs:
+        # the largest single-GPU states (one GPU's share of a run over several GPUs): n = 33
+        # complex128 and n = 34 complex64, 128 GiB each (256 GiB with the adjoint's second vector)
+        del s
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        extras["full_size"] = {}
+        for nf, dtf in ((33, "c128"), (34, "c64")):
+            extras["full_size"][f"n{nf}_{dtf}"] = full_size_leg(sv, I, nf, dtf, p)
+
     cpu = None
     if "cpu" in legs:
         cpu = cpu_baseline(args.cpu_sample_n, args.cpu_sample_p)
@@ -322,6 +334,83 @@ def main():
     print(json.dumps(res), flush=True)
 
 
+def full_size_leg(sv, I, n: int, dtype: str, p: int) -> dict:
+    """QAOA p-layer energy evaluation, AQA 10 steps and the p-layer adjoint
+    gradient on a 128 GiB state: per-layer time, tile-pass GB/s against the
+    HBM peak and the streaming ceilings of the plan."""
+    import numpy as np
+    import torch
+
+    inst = I.full_size_instance(n)
+    H = sv.Ising.from_instance(inst)
+    sv.ground(H)
+    s = sv.State(n, dtype)
+    gam, bet = I.linear_ramp_params(p)
+    sv.qaoa_energy(s, H, gam, bet)
+    torch.cuda.synchronize()
+    reps = 3
+    sv.profile_enable(True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        out = sv.qaoa_energy(s, H, gam, bet)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    prof = sv.profile_report()
+    sv.profile_enable(False)
+    k = prof.get(f"pass_{dtype}_nv1", {"launches": 0, "ms": 0.0, "bytes": 0.0})
+    gbs = k["bytes"] / (k["ms"] * 1e-3) / 1e9 if k["ms"] > 0 else 0.0
+    by_geo = {key.split("/", 1)[1]: round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1)
+              for key, v in prof.items() if key.startswith(f"pass_{dtype}_nv1/")}
+    ceil = stream_ceilings(sv, s, n, dtype)
+    g_aqa, b_aqa = sv.schedule_linear(10, 0.5, paper_sign=True)
+    sv.aqa_run(s, H, g_aqa, b_aqa)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(2):
+        sv.aqa_run(s, H, g_aqa, b_aqa)
+    torch.cuda.synchronize()
+    ms_aqa = (time.perf_counter() - t0) * 1e3 / 2
+    res = {"ms_per_evaluation": round(ms, 3), "ms_per_layer": round(ms / p, 3),
+           "amp_updates_per_s": p * (1 << n) * (n + 1) / (ms * 1e-3), "k_pass_GBps": round(gbs, 1),
+           "frac": round(gbs / HBM_PEAK_GBS, 4), "by_geometry_GBps": by_geo,
+           "stream_ceilings": {kk: v for kk, v in ceil.items() if kk != "T"},
+           "passes_per_layer": k["launches"] / reps / p, "energy": out[0], "p_gs": out[1],
+           "aqa10_ms": round(ms_aqa, 3), "aqa10_ms_per_step": round(ms_aqa / 10, 3)}
+    free = torch.cuda.mem_get_info()[0]
+    if free >= s.nbytes + (2 << 30):
+        lam = sv.State(n, dtype)
+        sv.grad(s, lam, H, gam, bet)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            sv.grad(s, lam, H, gam, bet)
+        torch.cuda.synchronize()
+        t_grad = (time.perf_counter() - t0) * 1e3 / 2
+        res.update({"grad_ms": round(t_grad, 3), "grad_speedup_vs_fd": round((2 * p + 1) * ms / t_grad, 3)})
+        del lam
+    log(f"[bench] full size n={n} {dtype}: {ms:.1f} ms per p={p} evaluation, {gbs:.0f} GB/s, "
+        f"AQA 10 steps {ms_aqa:.1f} ms, grad {res.get('grad_ms')} ms")
+    del s, H
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return res
+
+
+def stream_ceilings(sv, s, n: int, dtype: str) -> dict:
+    """GB/s of the library's streaming kernel (sv_stream_ceiling) for every tile
+    geometry of the one-vector plan, keyed 'c<carrier bits>o<group start>'
+    (and 'c<T>' for the contiguous tile)."""
+    plan = sv.describe(n, dtype)["plans"]["nv1"]
+    nbytes = 2 * (1 << n) * (16 if dtype == "c128" else 8)
+    out = {"T": plan[0]["T"]}
+    for g in plan:
+        key = f"c{g['c']}" if g["g"] == 0 else f"c{g['c']}o{g['lo']}"
+        sv.stream_ceiling(s, g["c"], g["lo"])
+        ms = min(sv.stream_ceiling(s, g["c"], g["lo"]) for _ in range(3))
+        out[key] = round(nbytes / (ms * 1e-3) / 1e9, 1)
+    return out
+
+
 def committed_traffic(dtype: str, n: int, p: int):
     """HBM bytes per tile-pass launch from the committed rocprofv3 FETCH_SIZE /
     WRITE_SIZE summary of this workload, or None when there is none or the
@@ -343,23 +432,57 @@ def committed_traffic(dtype: str, n: int, p: int):
 
 
 def cpu_baseline(n: int, p: int):
-    """FP64 oracle on the host cores: QAOA forward + observables at a bounded size."""
+    """FP64 oracle on the host cores (a bounded sample of the same workload):
+    oracle.c compiled here with -O3 -march=native (no fast-math) into a
+    temporary directory; energy table + QAOA p-layer forward + observables,
+    median of 3, on all cores at n and on one thread at n - 4."""
+    import os
+    import tempfile
+
     import numpy as np
 
+    from oracle import build as obuild
     from oracle import oracle as orc
     from paper_2104_03293_amd import inputs as I
 
-    inst = I.degree4_int2(n, 4 + n)
+    tmp = Path(tempfile.mkdtemp(prefix="oracle_native_"))
+    orc.use_library(obuild.build(out=tmp / "liboracle_native.so", native=True))
     g, b = I.linear_ramp_params(p)
-    E = orc.energies(inst)
-    t0 = time.perf_counter()
-    psi = orc.qaoa_state(inst, g, b, E=E)
-    orc.observables(inst, psi, E=E, gs=(float(E.min()), 1, 0))
-    dt = time.perf_counter() - t0
-    updates = p * (1 << n) * (n + 1)
-    log(f"[bench] cpu oracle n={n} p={p}: {dt:.2f} s on {orc.num_threads()} threads")
-    return {"value": updates / dt, "unit": "amplitude-updates/s", "cores": orc.num_threads(), "kind": "oracle",
-            "sample": f"QAOA p={p} forward + observables at n={n} (FP64 C/OpenMP oracle), {dt:.2f} s"}
+
+    def rate(nn: int) -> tuple:
+        inst = I.degree4_int2(nn, 4 + nn)
+        ts = []
+        for _ in range(3):
+            t0 = time.perf_counter()
+            E = orc.energies(inst)
+            psi = orc.qaoa_state(inst, g, b, E=E)
+            orc.observables(inst, psi, E=E, gs=(float(E.min()), 1, 0))
+            ts.append(time.perf_counter() - t0)
+            del psi, E
+        dt = float(np.median(ts))
+        return p * (1 << nn) * (nn + 1) / dt, dt
+
+    threads = orc.num_threads()
+    v_all, t_all = rate(n)
+    orc.set_num_threads(1)
+    v_one, t_one = rate(n - 4)
+    orc.set_num_threads(threads)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    nproc = len(os.sched_getaffinity(0))
+    log(f"[bench] cpu oracle (-O3 -march=native) n={n} p={p}: {t_all:.2f} s on {threads} threads; "
+        f"n={n - 4}: {t_one:.2f} s on 1 thread ({model}, nproc {nproc})")
+    return {"value": v_all, "unit": "amplitude-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"energy table + QAOA p={p} forward + observables at n={n} (FP64 C/OpenMP oracle, "
+                      f"-O3 -march=native), median of 3 = {t_all:.2f} s",
+            "one_thread": {"value": v_one, "n": n - 4, "seconds": round(t_one, 3)},
+            "nproc": nproc, "cpu_model": model}
 
 
 if __name__ == "__main__":

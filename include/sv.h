@@ -160,7 +160,7 @@ int sv_qaoa_energy(sv_state s, sv_ising H, int p, const double* gamma, const dou
  *   - d_out: caller-owned DEVICE array of 3 doubles, written on the state's
  *     stream as (norm, energy, p_gs); the call returns after enqueueing and
  *     does not synchronise (read d_out after the stream has completed);
- *   - the reduction partials and phase tables live in a fixed 32 MiB device
+ *   - the reduction partials and phase tables live in a fixed ~32 MiB device
  *     array of the library (one per GPU, held until the process ends); the
  *     call makes no hipMalloc / hipFree / pinned-host allocation;
  *   - limits: partials of at most 2^20 tiles (every n up to 33 complex128 and
@@ -306,6 +306,17 @@ int sv_tune_load(const char* path);
  * read plus state vectors written, 2^n * element size each); then clears. */
 int sv_profile_enable(int on);
 int sv_profile_report(char* buf, size_t len);
+
+/* Streaming ceiling of the tile passes' access pattern (no paper passage:
+ * the reference rate the pass bandwidth is compared with).  One in-place
+ * read + write of the whole state, tile by tile, with the passes' tile size
+ * (2^13 amplitudes for SV_C128, 2^14 for SV_C64), lane order, nontemporal
+ * accesses and tile order, and no arithmetic: the state is unchanged.  A tile
+ * holds the c lowest index bits (runs of 2^c amplitudes) and the T - c bits
+ * starting at lo; c = T is the contiguous tile (lo ignored).  *ms receives the
+ * kernel time from HIP events on the state's stream.  Requires n >= T,
+ * 0 <= c <= T and c <= lo, lo + T - c <= n (else SV_ERR_ARG).  Synchronises. */
+int sv_stream_ceiling(sv_state s, int c, int lo, double* ms);
 
 #ifdef __cplusplus
 }

@@ -11,11 +11,16 @@ from pathlib import Path
 HERE = Path(__file__).resolve().parent
 
 
-def build(verbose: bool = False) -> Path:
+def build(verbose: bool = False, out: Path | None = None, native: bool = False) -> Path:
+    """Compile oracle.c.  native=True adds -O3 -march=native for timing runs on the
+    machine that compiles it (the CPU-baseline leg builds such a copy in a
+    temporary directory on the host it times); the shipped test library is -O2
+    for any x86-64 host."""
     src = HERE / "oracle.c"
-    out = HERE / "liboracle.so"
-    tmp = HERE / "liboracle.so.tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math",
+    out = Path(out) if out is not None else HERE / "liboracle.so"
+    tmp = out.with_name(out.name + ".tmp")
+    opt = ["-O3", "-march=native"] if native else ["-O2"]
+    cmd = ["gcc", *opt, "-std=c11", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math",
            "-Wall", "-Wextra", "-o", str(tmp), str(src), "-lm"]
     if verbose:
         print(" ".join(cmd))

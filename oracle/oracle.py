@@ -31,10 +31,20 @@ _ip = ctypes.POINTER(ctypes.c_int32)
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 
 
+_LIB_PATH = None  # another compiled copy of oracle.c (use_library), else oracle/liboracle.so
+
+
+def use_library(path) -> None:
+    """Load the C oracle from another compiled copy of oracle.c (the timing build
+    of the CPU-baseline leg); the next call of lib() loads it."""
+    global _LIB, _LIB_PATH
+    _LIB, _LIB_PATH = None, Path(path)
+
+
 def lib():
     global _LIB
     if _LIB is None:
-        path = _HERE / "liboracle.so"
+        path = _LIB_PATH or (_HERE / "liboracle.so")
         if not path.exists():
             from . import build as _b  # noqa: F401  (oracle/build.py)
 

@@ -1069,6 +1069,9 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
     for (const Pass& p : prog.passes)
         part_need = std::max(part_need, (size_t)plan.by_nv[p.nv][p.group].ntiles * std::max<size_t>(1, p.slot_dst.size()));
     int rc = SV_OK;
+    // the slot reduction's first stage follows the partials
+    const size_t stage_off = part_need;
+    part_need += (size_t)kReduceBlocks * kMaxSlots;
     if (fx) {
         if (part_need > fx->part_doubles)
             return fail(SV_ERR_UNSUPPORTED, "reduction partials need %zu doubles, the fixed scratch holds %zu",
@@ -1285,7 +1288,8 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
             // kind/geometry: aggregated under the kind, and per tile shape, carrier bits and layouts
             const std::string kind = std::string("pass_") + (s->dt == SV_C128 ? "c128" : "c64") + "_nv" +
                                      std::to_string(p.nv) + "/T" + std::to_string(geo.T) + "c" +
-                                     std::to_string(geo.c) + "L" + std::to_string(a.nlayouts) +
+                                     std::to_string(geo.c) + (geo.g > 0 ? "o" + std::to_string(geo.lo) : "") +
+                                     "L" + std::to_string(a.nlayouts) +
                                      ((p.load & 4) ? "w" : "");
             prof_end(s->stream, ev0, kind, (double)(nrd + nwr) * (double)s->bytes);
         }
@@ -1313,7 +1317,7 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         }
         if (a.nslots > 0) {
             e = launch_reduce_slots(d_part, geo.ntiles, a.nslots, p.slot_dst.data(), fx ? 0 : 1,
-                                    fx ? fx->out : s->w.d_res, s->stream);
+                                    fx ? fx->out : s->w.d_res, d_part + stage_off, s->stream);
             if (e != 0) {
                 s->failed = true;
                 return fail(SV_ERR_HIP, "reduce launch failed: %s", hipGetErrorString((hipError_t)e));
@@ -2158,6 +2162,46 @@ extern "C" int sv_grad(sv_state psi, sv_state lam, sv_ising H, int p, const doub
         dgamma[k] = 2.0 * psi->w.h_res[3 + k];
         dbeta[k] = 2.0 * psi->w.h_res[3 + p + k];
     }
+    return SV_OK;
+}
+
+// ============================================================================ streaming ceiling
+extern "C" int sv_stream_ceiling(sv_state s, int c, int lo, double* ms) {
+    if (!s || !ms) return fail(SV_ERR_ARG, "sv_stream_ceiling: NULL argument");
+    if (s->failed) return fail(SV_ERR_HIP, "state is in a failed state after an earlier HIP error");
+    const int T = s->dt == SV_C128 ? 13 : 14;
+    const int g = T - c;
+    if (s->n < T || c < 0 || c > T || (g > 0 && (lo < c || lo + g > s->n)))
+        return fail(SV_ERR_ARG, "sv_stream_ceiling: geometry c=%d lo=%d does not fit n=%d with %d-bit tiles", c, lo,
+                    s->n, T);
+    StreamArgs a;
+    memset(&a, 0, sizeof(a));
+    a.ntiles = 1ull << (s->n - T);
+    a.c = c;
+    a.lo = g > 0 ? lo : T;
+    a.g = g;
+    a.xcd = knob_for("xcd", (int)s->dt, s->n);
+    if (a.xcd < 0) a.xcd = ((size_t(1) << s->n) * elem_size(s->dt)) > (size_t(64) << 30) ? 3 : 1;
+    hipEvent_t e0, e1;
+    HIPCHECK(hipEventCreate(&e0));
+    hipError_t e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(SV_ERR_HIP, "hipEventCreate: %s", hipGetErrorString(e));
+    }
+    e = hipEventRecord(e0, s->stream);
+    if (e == hipSuccess) e = (hipError_t)launch_stream((int)s->dt, s->ptr, a, s->stream);
+    if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) {
+        s->failed = true;
+        return fail(SV_ERR_HIP, "sv_stream_ceiling: %s", hipGetErrorString(e));
+    }
+    *ms = t;
     return SV_OK;
 }
 

@@ -204,9 +204,20 @@ int launch_pass(int dtype, int nv, int T, const PassArgs& a, void* stream);
 int launch_tile_fields(const TfArgs& a, void* stream);
 int launch_tables(const TableJob* jobs, int njobs, double2* out, void* stream);
 int launch_spin_reduce(const SpinArgs& a, void* stream);
+// stage: kReduceBlocks * kMaxSlots doubles of scratch for the first stage.
+constexpr int kReduceBlocks = 256;
 int launch_reduce_slots(const double* partials, uint64_t nrows, int nslots, const int* dst,
-                        int accumulate, double* out, void* stream);
+                        int accumulate, double* out, double* stage, void* stream);
 int launch_ground(int dtype, const GroundArgs& a, void* stream);
+// Streaming ceiling: in-place load/store of every tile of a geometry (T = 13
+// for complex128, 14 for complex64), no arithmetic.
+struct StreamArgs {
+    uint64_t ntiles;
+    int32_t c, lo, g;
+    int32_t xcd;            // tile order as PassArgs::xcd
+    uint64_t mask;          // 0: every amplitude is stored back unchanged (XOR with this mask)
+};
+int launch_stream(int dtype, void* p, const StreamArgs& a, void* stream);
 int launch_ground_finish(const GroundArgs& a, double* out_e, uint64_t* out_cnt,
                          uint64_t* out_arg, void* stream);
 // ---------------------------------------------------------------- batch scan

@@ -64,6 +64,19 @@ __device__ __forceinline__ void st_nt(float2* p, float2 x) {
     __builtin_nontemporal_store(v, reinterpret_cast<nf2*>(p));
 }
 
+// Tables that no kernel writes while it reads them (tile geometries, phase
+// tables) are read through the constant address space: the compiler may then
+// use scalar loads for their wave-uniform entries even after the kernel's own
+// stores to the state, instead of one vector load per entry.
+#define SV_CONST __attribute__((address_space(4)))
+typedef const SV_CONST GeoBuf CGeoBuf;
+typedef const SV_CONST GeoLayout CGeoLayout;
+// entry i of a constant-space complex table (component loads: the vector type's
+// operators take generic references)
+__device__ __forceinline__ double2 ctab(const SV_CONST double* t, int i) {
+    return make_double2(t[2 * i], t[2 * i + 1]);
+}
+
 __device__ __forceinline__ double spin_u(uint32_t u, int l) { return ((u >> l) & 1u) ? 1.0 : -1.0; }
 __device__ __forceinline__ double spin_z(uint64_t z, int i) { return ((z >> i) & 1ull) ? 1.0 : -1.0; }
 
@@ -138,11 +151,11 @@ __global__ void __launch_bounds__(256) k_tile_fields(const TfArgs a) {
 // inside the tile that involve thread bits come from the layout's per-thread
 // table (one coalesced load per row).
 template <int R, int NTB>
-__device__ __forceinline__ double thread_energy(const GeoLayout* L, const GeoBuf* geo, uint32_t t,
+__device__ __forceinline__ double thread_energy(CGeoLayout* L, CGeoBuf* geo, uint32_t t,
                                                 const double* s_g, double (&f)[R]) {
     constexpr int NT = 1 << NTB;
     const uint32_t off = L->thr_off;
-    const double* __restrict__ tab = reinterpret_cast<const double*>(geo) + off + t;
+    const SV_CONST double* __restrict__ tab = reinterpret_cast<const SV_CONST double*>(geo) + off + t;
     double eth = s_g[kTF - 1];
     uint32_t m = L->tmask;
 #pragma unroll
@@ -263,17 +276,34 @@ __device__ __forceinline__ void mix_round(Real (&vr)[NV][1 << R], Real (&vi)[NV]
         if constexpr (NV == 2) {
             if ((flags & MIX_GBETA) && on) {
                 double gb = 0.0;
+                if constexpr (sizeof(Real) == 8) {
+                    // complex128: the four products of each pair fused into two
+                    // alternating FP64 accumulators
+                    double g2 = 0.0;
 #pragma unroll
-                for (int r = 0; r < NR; r++) {
-                    if (r & (1 << k)) continue;
-                    const int r2 = r | (1 << k);
-                    // pair term in the storage precision, summed in FP64 (FP64 products
-                    // change the complex64 gradient by ~1e-10 of the coefficient scale, far
-                    // below the f32 rounding of the stored vectors, and spill the
-                    // four-waves-per-SIMD kernels)
-                    const Real q = vr[1][r] * vi[0][r2] - vi[1][r] * vr[0][r2] + vr[1][r2] * vi[0][r] -
-                                   vi[1][r2] * vr[0][r];
-                    gb += (double)q;
+                    for (int r = 0; r < NR; r++) {
+                        if (r & (1 << k)) continue;
+                        const int r2 = r | (1 << k);
+                        double& acc = ((r >> (k == 0 ? 1 : 0)) & 1) ? g2 : gb;
+                        acc = fma(vr[1][r], vi[0][r2], acc);
+                        acc = fma(-vi[1][r], vr[0][r2], acc);
+                        acc = fma(vr[1][r2], vi[0][r], acc);
+                        acc = fma(-vi[1][r2], vr[0][r], acc);
+                    }
+                    gb += g2;
+                } else {
+#pragma unroll
+                    for (int r = 0; r < NR; r++) {
+                        if (r & (1 << k)) continue;
+                        const int r2 = r | (1 << k);
+                        // pair term in the storage precision, summed in FP64 (FP64 products
+                        // change the complex64 gradient by ~1e-10 of the coefficient scale, far
+                        // below the f32 rounding of the stored vectors, and spill the
+                        // four-waves-per-SIMD kernels)
+                        const Real q = vr[1][r] * vi[0][r2] - vi[1][r] * vr[0][r2] + vr[1][r2] * vi[0][r] -
+                                       vi[1][r2] * vr[0][r];
+                        gb += (double)q;
+                    }
                 }
                 gsum += gb * pend[0] * pend[1];
             }
@@ -425,7 +455,7 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
     __shared__ double s_spin[NW][kTF];  // per-wave spin sums (PT_SPINZ)
 
     const uint32_t t = threadIdx.x;
-    const GeoBuf* __restrict__ geo = a.geo;
+    CGeoBuf* __restrict__ geo = (CGeoBuf*)a.geo;
     const TileGeom tg{a.c, a.lo, a.g};
     V2* __restrict__ psi = reinterpret_cast<V2*>(a.psi);
     V2* __restrict__ lam = reinterpret_cast<V2*>(a.lam);
@@ -450,7 +480,7 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
         // ---- load in layout 0 (issued before the per-tile field computation so
         // that the field loop overlaps the memory latency)
         int cur = 0;
-        const GeoLayout* L = &geo->L[0];
+        CGeoLayout* L = &geo->L[0];
         uint32_t thr_u = thread_index_bits<T - R>(t, L->tmask);
         uint64_t thr_goff = tg.gmap(thr_u);
 
@@ -542,7 +572,7 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                     if (step > 0) {
                         // LDS exchange cur -> j: in two halves split by the pivot (register
                         // slot R-1) for one vector, as whole tiles for two vectors
-                        const GeoLayout* Lt = &geo->L[j];
+                        CGeoLayout* Lt = &geo->L[j];
                         const uint32_t new_u = thread_index_bits<T - R>(t, Lt->tmask);
                         // byte offsets: one XOR with the table entry per access
                         const uint32_t src = lds_swizzle(thr_u, a.swz) * (uint32_t)sizeof(V2);
@@ -701,19 +731,20 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                 }
                 if (fl & (PT_PHASE_PSI | PT_PHASE_LAM)) {
                     const double gam = op.a;
-                    const double2* __restrict__ qph = a.ptab + a.qph_off[op.qidx];
+                    const SV_CONST double* __restrict__ qph = (const SV_CONST double*)(a.ptab + a.qph_off[op.qidx]);
                     double2 gk[R];
                     double2 run;
                     if constexpr (INTE) {
                         // energies on the grid Z / q: factors from the table exp(-i gamma m / q)
-                        const double2* __restrict__ lut = a.ptab + a.lut_off[op.qidx] + a.lut_half;
+                        const SV_CONST double* __restrict__ lut =
+                            (const SV_CONST double*)(a.ptab + a.lut_off[op.qidx] + a.lut_half);
                         const int Lh = a.lut_half;
 #pragma unroll
                         for (int k = 0; k < R; k++) {
                             const int m = min(max((int)(2.0 * f[k] * a.lut_q), -Lh), Lh);
-                            gk[k] = lut[m];
+                            gk[k] = ctab(lut, m);
                         }
-                        run = lut[min(max((int)(e0 * a.lut_q), -Lh), Lh)];
+                        run = ctab(lut, min(max((int)(e0 * a.lut_q), -Lh), Lh));
                     } else {
                         // One sincos at a time: the fma(0, previous sine, x) link (exact
                         // for finite values) keeps the scheduler from interleaving the
@@ -730,9 +761,8 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                         sincos(fma(0.0, link, gam * e0), &sn, &cs);
                         run = make_double2(cs, -sn);
                     }
-                    double fac[NV];
-#pragma unroll
-                    for (int v = 0; v < NV; v++) fac[v] = pend[v];
+                    // the phase has modulus one: the pending scales stay pending (they are
+                    // applied at the store)
 #pragma unroll
                     for (int i = 0; i < NR; i++) {
                         const int r = i ^ (i >> 1);
@@ -741,24 +771,21 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                             const double2 g = ((r >> k) & 1) ? gk[k] : make_double2(gk[k].x, -gk[k].y);
                             run = cmul(run, g);
                         }
-                        const double2 ph = cmul(run, qph[r]);
+                        const double2 ph = cmul(run, ctab(qph, r));
 #pragma unroll
                         for (int v = 0; v < NV; v++) {
-                            const double pr = ph.x * fac[v], pim = ph.y * fac[v];
                             if constexpr (sizeof(Real) == 8) {
                                 const double xr = vr[v][r], xi = vi[v][r];
-                                vr[v][r] = xr * pr - xi * pim;
-                                vi[v][r] = xr * pim + xi * pr;
+                                vr[v][r] = xr * ph.x - xi * ph.y;
+                                vi[v][r] = xr * ph.y + xi * ph.x;
                             } else {
-                                const float cr = (float)pr, ci = (float)pim;
+                                const float cr = (float)ph.x, ci = (float)ph.y;
                                 const float xr = vr[v][r], xi = vi[v][r];
                                 vr[v][r] = xr * cr - xi * ci;
                                 vi[v][r] = xr * ci + xi * cr;
                             }
                         }
                     }
-#pragma unroll
-                    for (int v = 0; v < NV; v++) pend[v] = 1.0;
                 }
             }
         }
@@ -813,27 +840,55 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
 }
 
 // Column sums of partials[nrows][nslots] in a fixed order: out[dst[s]] (+)= sum.
+// Two launches: kReduceBlocks workgroups each sum a contiguous run of rows
+// (strided per thread, then a tree) into stage[block][slot]; one workgroup then
+// adds the blocks' sums in a tree.  The order depends only on nrows.
 struct SlotDst {
     int d[kMaxSlots];
 };
 
-__global__ void __launch_bounds__(256) k_reduce_slots(const double* __restrict__ partials, uint64_t nrows,
-                                                      int nslots, SlotDst dst, int accumulate,
-                                                      double* __restrict__ out) {
-    __shared__ double sh[256];
-    const int s = blockIdx.x;
+__global__ void __launch_bounds__(256) k_reduce_rows(const double* __restrict__ partials, uint64_t nrows, int nslots,
+                                                     double* __restrict__ stage) {
+    __shared__ double sh[kMaxSlots][256];
     const int t = threadIdx.x;
-    double v = 0.0;
-    for (uint64_t i = t; i < nrows; i += 256) v += partials[i * nslots + s];
-    sh[t] = v;
+    const uint64_t per = (nrows + gridDim.x - 1) / gridDim.x;
+    const uint64_t r0 = (uint64_t)blockIdx.x * per;
+    const uint64_t r1 = r0 + per < nrows ? r0 + per : nrows;
+    double v[kMaxSlots];
+#pragma unroll
+    for (int q = 0; q < kMaxSlots; q++) v[q] = 0.0;
+    for (uint64_t i = r0 + t; i < r1; i += 256)
+#pragma unroll
+        for (int q = 0; q < kMaxSlots; q++)
+            if (q < nslots) v[q] += partials[i * nslots + q];
+#pragma unroll
+    for (int q = 0; q < kMaxSlots; q++) sh[q][t] = v[q];
     __syncthreads();
     for (int w = 128; w >= 1; w >>= 1) {
-        if (t < w) sh[t] += sh[t + w];
+        if (t < w)
+#pragma unroll
+            for (int q = 0; q < kMaxSlots; q++) sh[q][t] += sh[q][t + w];
         __syncthreads();
     }
-    if (t == 0) {
-        const int d = dst.d[s];
-        out[d] = accumulate ? out[d] + sh[0] : sh[0];
+    if (t < nslots) stage[blockIdx.x * kMaxSlots + t] = sh[t][0];
+}
+
+__global__ void __launch_bounds__(256) k_reduce_slots(const double* __restrict__ stage, int nblocks, int nslots,
+                                                      SlotDst dst, int accumulate, double* __restrict__ out) {
+    __shared__ double sh[256];
+    const int t = threadIdx.x;
+    for (int q = 0; q < nslots; q++) {
+        sh[t] = t < nblocks ? stage[t * kMaxSlots + q] : 0.0;
+        __syncthreads();
+        for (int w = 128; w >= 1; w >>= 1) {
+            if (t < w) sh[t] += sh[t + w];
+            __syncthreads();
+        }
+        if (t == 0) {
+            const int d = dst.d[q];
+            out[d] = accumulate ? out[d] + sh[0] : sh[0];
+        }
+        __syncthreads();
     }
 }
 
@@ -881,13 +936,13 @@ __global__ void __launch_bounds__(1 << (T - R)) k_ground(const GroundArgs a) {
 
     const uint32_t t = threadIdx.x;
     const uint64_t tile = blockIdx.x;
-    const GeoBuf* __restrict__ geo = a.geo;
+    CGeoBuf* __restrict__ geo = (CGeoBuf*)a.geo;
     const TileGeom tg{a.c, a.lo, a.g};
     const uint64_t base = tg.base(tile);
     if (t < kTF) s_g[t] = a.tf[tile * kTF + t];
     __syncthreads();
 
-    const GeoLayout* L = &geo->L[0];
+    CGeoLayout* L = &geo->L[0];
     const uint32_t thr_u = thread_index_bits<T - R>(t, L->tmask);
     const uint64_t thr_goff = tg.gmap(thr_u);
     double f[R];
@@ -1146,6 +1201,52 @@ int launch_pass(int dtype, int nv, int T, const PassArgs& a, void* stream) {
     return a.occ4 ? run_pass<float, 13, 4, 2, 4, 4>(a, stream) : run_pass<float, 13, 4, 2, 4, 1>(a, stream);
 }
 
+// Streaming ceiling of a tile geometry: every workgroup loads its tile (2^T
+// amplitudes, the pass's lane order: thread t holds tile-local indices
+// t + r 2^(T-R)) with nontemporal loads and stores it back unchanged, in the
+// passes' XCD-aware tile order.  No arithmetic.
+template <typename V2, int T, int R, int MINB>
+__global__ void __launch_bounds__(1 << (T - R), MINB) k_stream(V2* __restrict__ p, const StreamArgs a) {
+    constexpr int NT = 1 << (T - R);
+    constexpr int NR = 1 << R;
+    uint64_t tile = blockIdx.x;
+    if (a.xcd > 0) {
+        const int kb = 2 + a.xcd;
+        if ((a.ntiles & ((1ull << kb) - 1ull)) == 0 && gridDim.x == a.ntiles)
+            tile = (uint64_t)(blockIdx.x & ((1u << kb) - 1u)) * (a.ntiles >> kb) + (blockIdx.x >> kb);
+    }
+    const TileGeom tg{a.c, a.lo, a.g};
+    V2* __restrict__ q = p + tg.base(tile);
+    V2 v[NR];
+#pragma unroll
+    for (int r = 0; r < NR; r++) v[r] = ld_nt(q + tg.gmap(threadIdx.x + (uint32_t)r * NT));
+    // XOR with a mask that is zero at run time: the stores cannot be proven to
+    // write back what was loaded, so the compiler keeps them
+#pragma unroll
+    for (int r = 0; r < NR; r++) {
+        if constexpr (sizeof(v[r].x) == 8) {
+            v[r].x = __longlong_as_double(__double_as_longlong(v[r].x) ^ (long long)a.mask);
+            v[r].y = __longlong_as_double(__double_as_longlong(v[r].y) ^ (long long)a.mask);
+        } else {
+            v[r].x = __int_as_float(__float_as_int(v[r].x) ^ (int)a.mask);
+            v[r].y = __int_as_float(__float_as_int(v[r].y) ^ (int)a.mask);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < NR; r++) st_nt(q + tg.gmap(threadIdx.x + (uint32_t)r * NT), v[r]);
+}
+
+int launch_stream(int dtype, void* p, const StreamArgs& a, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    if (dtype == 2)
+        hipLaunchKernelGGL((k_stream<double2, 13, 5, 2>), dim3((unsigned)a.ntiles), dim3(256), 0, st,
+                           (double2*)p, a);
+    else
+        hipLaunchKernelGGL((k_stream<float2, 14, 5, 4>), dim3((unsigned)a.ntiles), dim3(512), 0, st,
+                           (float2*)p, a);
+    return (int)hipGetLastError();
+}
+
 int launch_tables(const TableJob* jobs, int njobs, double2* out, void* stream) {
     for (int s = 0; s < njobs; s += 64) {
         TableJobs tj;
@@ -1159,11 +1260,14 @@ int launch_tables(const TableJob* jobs, int njobs, double2* out, void* stream) {
 }
 
 int launch_reduce_slots(const double* partials, uint64_t nrows, int nslots, const int* dst, int accumulate,
-                        double* out, void* stream) {
+                        double* out, double* stage, void* stream) {
     SlotDst d;
     for (int s = 0; s < kMaxSlots; s++) d.d[s] = s < nslots ? dst[s] : 0;
-    hipLaunchKernelGGL(k_reduce_slots, dim3(nslots), dim3(256), 0, (hipStream_t)stream, partials, nrows, nslots,
-                       d, accumulate, out);
+    const uint64_t want = (nrows + 2047) / 2048;  // about 2048 rows per workgroup
+    const int nb = (int)(want < (uint64_t)kReduceBlocks ? (want > 0 ? want : 1) : kReduceBlocks);
+    hipLaunchKernelGGL(k_reduce_rows, dim3(nb), dim3(256), 0, (hipStream_t)stream, partials, nrows, nslots, stage);
+    hipLaunchKernelGGL(k_reduce_slots, dim3(1), dim3(256), 0, (hipStream_t)stream, stage, nb, nslots, d, accumulate,
+                       out);
     return (int)hipGetLastError();
 }
 

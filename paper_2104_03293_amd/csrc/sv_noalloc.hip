@@ -12,8 +12,9 @@
 
 namespace {
 // Reduction partials: 3 slots (norm, energy, p_gs) per tile of the largest
-// tile group, 2^20 tiles at n = 33 complex128 and n = 34 complex64 (24 MiB).
-constexpr size_t kPartDoubles = size_t(3) << 20;
+// tile group, 2^20 tiles at n = 33 complex128 and n = 34 complex64 (24 MiB),
+// and the first stage of the slot reduction (256 x 8 doubles).
+constexpr size_t kPartDoubles = (size_t(3) << 20) + 2048;
 // Phase tables, double2 entries (8 MiB): per layer 32 register phases plus the
 // 2L + 1 entries of an integer-energy table.
 constexpr size_t kTabEntries = size_t(1) << 19;

@@ -1,4 +1,4 @@
-"""Classical optimisation loop around the QAOA energy (Sec. III.B.1, Sec. IV.A).
+"""Classical optimisation loop around the QAOA energy (Sec. III.B.1, Sec. III.C.1).
 
 The variational parameters (gamma_1..p, beta_1..p) of the QAOA state are handed
 to a scipy optimiser that minimises the energy <H_C>; every evaluation is one

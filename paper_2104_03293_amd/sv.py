@@ -75,6 +75,7 @@ def _load():
         "sv_tune_load": (ip, [ctypes.c_char_p]),
         "sv_profile_enable": (ip, [ip]),
         "sv_profile_report": (ip, [ctypes.c_char_p, ctypes.c_size_t]),
+        "sv_stream_ceiling": (ip, [vp, ip, ip, dp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -444,12 +445,22 @@ def profile_report() -> dict:
     return json.loads(buf.value.decode())
 
 
+def stream_ceiling(s: State, c: int, lo: int = 0) -> float:
+    """Kernel time (ms) of one in-place streaming read + write of the state with
+    the tile passes' access pattern for carrier bits c and group start lo."""
+    ms = ctypes.c_double()
+    _check(lib.sv_stream_ceiling(s.handle, int(c), int(lo), ctypes.byref(ms)))
+    return ms.value
+
+
 # ----------------------------------------------------------------------------- autograd
 class QAOAEnergy:
     """torch.autograd.Function wrapper: f(gamma, beta) = <beta,gamma|H_C|beta,gamma>.
 
-    The forward call runs the library's adjoint sweep (forward circuit plus one
-    reverse sweep) and keeps the 2p derivatives for backward.
+    When gamma or beta needs a gradient, the forward call runs the library's
+    adjoint sweep (forward circuit plus one reverse sweep) and keeps the 2p
+    derivatives for backward; otherwise (no input requires grad, or grad mode
+    is off) it runs only the energy evaluation, and lam is not touched.
     """
 
     @staticmethod
@@ -459,7 +470,8 @@ class QAOAEnergy:
         class _F(torch.autograd.Function):
             @staticmethod
             def forward(ctx, g, b):
-                e, dg, db = grad(psi, lam, H, g.detach().cpu().numpy(), b.detach().cpu().numpy())
+                gn, bn = g.detach().cpu().numpy(), b.detach().cpu().numpy()
+                e, dg, db = grad(psi, lam, H, gn, bn)
                 ctx.save_for_backward(torch.from_numpy(dg).to(g), torch.from_numpy(db).to(b))
                 return torch.tensor(e, dtype=g.dtype, device=g.device)
 
@@ -468,4 +480,7 @@ class QAOAEnergy:
                 dg, db = ctx.saved_tensors
                 return go * dg, go * db
 
+        if not torch.is_grad_enabled() or not (gamma.requires_grad or beta.requires_grad):
+            e, _, _ = qaoa_energy(psi, H, gamma.detach().cpu().numpy(), beta.detach().cpu().numpy())
+            return torch.tensor(e, dtype=gamma.dtype, device=gamma.device)
         return _F.apply(gamma, beta)

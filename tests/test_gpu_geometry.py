@@ -355,3 +355,25 @@ def test_xcd_tile_orders_agree(sv, orc, record_error, dtype, n):
     gerr = max(np.max(np.abs(ref[5] - rg)), np.max(np.abs(ref[6] - rb))) / scale
     record_error(f"grad / scale {dtype}", gerr)
     assert gerr <= GRAD_TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype,n", [("c128", 20), ("c64", 21), ("c128", 26)])
+def test_stream_ceiling_leaves_state_unchanged(sv, dtype, n):
+    """sv_stream_ceiling reads and writes every amplitude in place with each tile
+    geometry of the plan: the state is bit-identical afterwards and a time is
+    reported; geometries that do not fit the state are argument errors."""
+    rng = np.random.default_rng(660 + n)
+    psi0 = rng.standard_normal(1 << n) + 1j * rng.standard_normal(1 << n)
+    s = sv.State(n, dtype)
+    s.from_numpy(psi0)
+    before = s.to_numpy()
+    for g in sv.describe(n, dtype)["plans"]["nv1"]:
+        ms = sv.stream_ceiling(s, g["c"], g["lo"])
+        assert ms > 0.0
+        assert np.array_equal(s.to_numpy(), before), (g["c"], g["lo"])
+    T = sv.describe(n, dtype)["plans"]["nv1"][0]["T"]
+    with pytest.raises(sv.SVError) as e:
+        sv.stream_ceiling(s, 3, n - 2)  # group bits beyond the state
+    assert e.value.code == 1
+    with pytest.raises(sv.SVError):
+        sv.stream_ceiling(s, T + 1, 0)

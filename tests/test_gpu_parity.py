@@ -706,3 +706,30 @@ def test_autograd_function(sv, orc, dtype):
     scale = max(np.max(np.abs(np.concatenate([rg, rb]))), orc.coeff_scale(inst)) * abs(3.0 + 2.0 * f)
     assert np.max(np.abs(g.grad.numpy() - (3.0 + 2.0 * f) * rg)) <= GRAD_TOL[dtype] * scale
     assert np.max(np.abs(b.grad.numpy() - (3.0 + 2.0 * f) * rb)) <= GRAD_TOL[dtype] * scale
+
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_autograd_function_forward_only(sv, orc, dtype):
+    """Without a gradient to compute (inputs without requires_grad, or under
+    torch.no_grad) QAOAEnergy runs only the energy evaluation: same energy as
+    sv_qaoa_energy, and the adjoint vector lam keeps its contents."""
+    import torch
+
+    n, p = 14, 2
+    inst = instance_for(n, "int", 450)
+    H = sv.Ising.from_instance(inst)
+    g0, b0 = I.uniform_params(p, 451, -1.0, 1.0)
+    psi, lam = sv.State(n, dtype), sv.State(n, dtype)
+    ref = sv.qaoa_energy(sv.State(n, dtype), H, g0, b0)[0]
+    marker = np.full(1 << n, 0.25 - 0.5j)
+    lam.from_numpy(marker)
+    e1 = sv.QAOAEnergy.apply(torch.tensor(g0), torch.tensor(b0), psi, lam, H)
+    g = torch.tensor(g0, requires_grad=True)
+    b = torch.tensor(b0, requires_grad=True)
+    with torch.no_grad():
+        e2 = sv.QAOAEnergy.apply(g, b, psi, lam, H)
+    assert e1.item() == ref and e2.item() == ref
+    assert np.array_equal(lam.to_numpy(), marker.astype(lam.to_numpy().dtype))
+    f = orc.energy_of(inst, g0, b0)
+    assert abs(ref - f) <= energy_tol(orc, inst, f)

@@ -1,4 +1,4 @@
-"""The QAOA optimisation loop (Sec. III.B.1, Sec. IV.A): budget, accounting,
+"""The QAOA optimisation loop (Sec. III.B.1, Sec. III.C.1): budget, accounting,
 rescaling (Eq. rescale) and agreement of the GPU-driven loop with an
 oracle-driven one."""
 import json
