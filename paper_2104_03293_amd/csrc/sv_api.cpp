@@ -72,6 +72,10 @@ std::map<std::string, int> g_knobs = {
     {"xcd", -1},      // x > 0: XCD-aware tile order, 8 * 2^(x-1) interleaved streams of contiguous tiles;
                       // 0: tile = workgroup index; -1: 8 streams for states up to 64 GiB, 32 above
                       // (n = 32 complex128: 241 -> 226 ms per p = 4 evaluation; n = 33: 589 -> 461 ms)
+    {"adjzeta", -1},  // adjoint: 1 = two one-vector reverse sweeps of psi +- i t lambda; 0 = one sweep of
+                      // both vectors (two-vector passes); -1 = 1 for complex128 (n = 32, p = 4: 731 vs
+                      // 767 ms), 0 for complex64 (449 vs 432 ms, and the f32 rounding of the two
+                      // sweeps does not cancel in their difference)
     {"c128t14", 0},   // complex128 one-vector programs (not the adjoint): 1 = 14-bit tiles (512 threads,
                       // one workgroup per CU), 0 = 13-bit tiles (256 threads, two workgroups per CU)
     {"fail_next_launch", 0},  // 1: the next tile-pass launch reports a launch failure (error-path tests)
@@ -81,7 +85,7 @@ const std::map<std::string, std::pair<int, int>> g_knob_range = {
     {"fuse", {0, 1}},    {"cmin64", {0, 8}},   {"cmin128", {0, 8}},  {"ntmin", {0, 64}},   {"persist", {0, 8}},
     {"stagger", {0, 64}}, {"snake", {0, 2}},   {"dpp", {0, 1}},      {"ldsswz", {3, 5}},   {"batchwide", {0, 2}},
     {"batch128", {0, 1}}, {"c64t13", {0, 1}},  {"c64occ", {0, 1}},   {"c64g4", {0, 1}},    {"kc34", {0, 1}},
-    {"c64g14", {0, 2}},  {"ntinit", {0, 1}},   {"split", {0, 1}},    {"xcd", {-1, 5}},      {"c128t14", {0, 1}},
+    {"c64g14", {0, 2}},  {"ntinit", {0, 1}},   {"split", {0, 1}},    {"xcd", {-1, 5}},      {"c128t14", {0, 1}}, {"adjzeta", {-1, 1}},
     {"fail_next_launch", {0, 1}},
 };
 int knob(const char* k) {
@@ -711,13 +715,13 @@ static int get_geobuf(const Geometry& geo, sv_ising_s* H, sv_dtype dt, GeoBuf** 
 
 // ============================================================================ programs
 // Events of a circuit, in application order.
-enum EvKind { EV_INIT, EV_PHASE, EV_MIX, EV_REDUCE, EV_LAMINIT, EV_GGAMMA, EV_SPINZ };
+enum EvKind { EV_INIT, EV_PHASE, EV_MIX, EV_REDUCE, EV_LAMINIT, EV_GGAMMA, EV_SPINZ, EV_E2, EV_ZETA, EV_EFORM };
 struct Event {
     EvKind kind;
     int group = 0;      // EV_MIX
-    double angle = 0;   // EV_PHASE gamma / EV_MIX beta
+    double angle = 0;   // EV_PHASE gamma / EV_MIX beta / EV_ZETA t
     int vec = 1;        // vectors touched (bit0 psi, bit1 lam)
-    int res = -1;       // result index (REDUCE: 3 consecutive; GGAMMA; MIX grad-beta)
+    int res = -1;       // result index (REDUCE: 3 consecutive; GGAMMA, E2, EFORM; MIX grad-beta)
     int gm = -1;        // EV_MIX: index of a general single-qubit layer (Program::layers), -1: exp(-i angle X)
 };
 
@@ -744,8 +748,8 @@ struct Program {
 static int point_rank(int flags) {
     // position of a POINT part in the kernel's fixed execution order
     if (flags & (PT_PHASE_PSI | PT_PHASE_LAM)) return 3;
-    if (flags & PT_GGAMMA) return 2;
-    if (flags & PT_LAM_INIT) return 1;
+    if (flags & (PT_GGAMMA | PT_EFORM)) return 2;
+    if (flags & (PT_LAM_INIT | PT_ZETA)) return 1;
     return 0;
 }
 
@@ -775,7 +779,7 @@ static Program build_program(const std::vector<Event>& evs, int nres, bool fuse)
         cur.ops.assign(kMaxOps, Op{});
         for (Op& o : cur.ops) {
             o.kind = 0;
-            o.slot = o.slot2 = o.qidx = -1;
+            o.slot = o.slot2 = o.slot3 = o.qidx = -1;
         }
         nmix_pre = nmix_post = 0;
         has_point = false;
@@ -862,7 +866,11 @@ static Program build_program(const std::vector<Event>& evs, int nres, bool fuse)
         if (e.kind == EV_LAMINIT) flag = PT_LAM_INIT;
         if (e.kind == EV_GGAMMA) flag = PT_GGAMMA;
         if (e.kind == EV_SPINZ) flag = PT_SPINZ;
-        const int slots = e.kind == EV_REDUCE ? 3 : (e.kind == EV_GGAMMA ? 1 : 0);
+        if (e.kind == EV_E2) flag = PT_E2;
+        if (e.kind == EV_ZETA) flag = PT_ZETA;
+        if (e.kind == EV_EFORM) flag = PT_EFORM;
+        const int slots =
+            e.kind == EV_REDUCE ? 3 : ((e.kind == EV_GGAMMA || e.kind == EV_E2 || e.kind == EV_EFORM) ? 1 : 0);
         bool merge = false;
         if (open && has_point && nmix_post == 0) {
             const Op& last = cur.ops[2];
@@ -873,7 +881,8 @@ static Program build_program(const std::vector<Event>& evs, int nres, bool fuse)
                 const int lastmax = point_rank(last.flags);
                 // (spin sums, like the reduction, read only |psi|^2)
                 merge = mine > lastmax ||
-                        ((flag == PT_REDUCE || flag == PT_SPINZ) && !(last.flags & (PT_LAM_INIT | PT_GGAMMA)));
+                        ((flag == PT_REDUCE || flag == PT_SPINZ || flag == PT_E2) &&
+                         !(last.flags & (PT_LAM_INIT | PT_GGAMMA | PT_ZETA)));
             }
         }
         bool fits = open && (!fuse ? !cur.has_mix : true) && (int)cur.slot_dst.size() + slots <= limit(e);
@@ -890,6 +899,7 @@ static Program build_program(const std::vector<Event>& evs, int nres, bool fuse)
             op.kind = OP_POINT;
             op.slot = -1;
             op.slot2 = -1;
+            op.slot3 = -1;
             op.qidx = -1;
             cur.ops[2] = op;
             has_point = true;
@@ -899,9 +909,14 @@ static Program build_program(const std::vector<Event>& evs, int nres, bool fuse)
         if (e.kind == EV_REDUCE) {
             op.slot = (int)cur.slot_dst.size();
             for (int q = 0; q < 3; q++) cur.slot_dst.push_back(e.res + q);
-        } else if (e.kind == EV_GGAMMA) {
+        } else if (e.kind == EV_GGAMMA || e.kind == EV_EFORM) {
             op.slot2 = (int)cur.slot_dst.size();
             cur.slot_dst.push_back(e.res);
+        } else if (e.kind == EV_E2) {
+            op.slot3 = (int)cur.slot_dst.size();
+            cur.slot_dst.push_back(e.res);
+        } else if (e.kind == EV_ZETA) {
+            op.b = e.angle;
         } else if (e.kind == EV_PHASE) {
             op.a = e.angle;
             op.qidx = (int)cur.phase.size();
@@ -1048,8 +1063,9 @@ static Plan make_plan(int n, sv_dtype dt, bool grad = false, bool general = fals
 // fixed device region fx describes, every result is written once, straight to
 // fx->out (no clearing), and the instance's tables and ground-state cache must
 // already exist; programs that need more (spin sums, general layers) are refused.
+// first_src: the first pass loads psi from this buffer instead of s (out of place).
 static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& prog, const Plan& plan,
-                       bool need_ground, const FixedScratch* fx = nullptr) {
+                       bool need_ground, const FixedScratch* fx = nullptr, const void* first_src = nullptr) {
     finalize_program(prog, plan.by_nv);
     if (s->failed) return fail(SV_ERR_HIP, "state is in a failed state after an earlier HIP error");
     double emin = 0.0, etol = 0.0;
@@ -1221,6 +1237,7 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
         PassArgs a;
         memset(&a, 0, sizeof(a));
         a.psi = s->ptr;
+        a.src = (pi == 0) ? first_src : nullptr;
         a.lam = lam ? lam->ptr : nullptr;
         a.partials = d_part;
         a.geo = gb;
@@ -1269,6 +1286,14 @@ static int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& p
             if (genblk[pi][i] >= 0) a.ops[i].qidx = genblk[pi][i];
         }
         a.gmat = p.gen ? s->w.d_gmat : nullptr;
+        // one-vector passes of the adjoint sweeps: 1 = quadratic forms only, 2 = also zeta / E form
+        a.qf = 0;
+        if (p.nv == 1)
+            for (const Op& op : p.ops) {
+                if (op.kind == OP_MIX && (op.flags & MIX_GBETA)) a.qf = std::max(a.qf, 1);
+                if (op.kind == OP_POINT && (op.flags & (PT_ZETA | PT_EFORM))) a.qf = std::max(a.qf, 2);
+                if (op.kind == OP_POINT && (op.flags & PT_ZETA) && (op.flags & PT_REDUCE)) a.qf = 3;
+            }
         a.kc34 = knob_for("kc34", (int)s->dt, s->n);
         a.occ4 = (s->dt == SV_C64 && p.nv == 2 && knob_for("c64g4", (int)s->dt, s->n) != 0) ? 1 : 0;
         if (s->dt == SV_C64 && geo.T == 14) {
@@ -2090,6 +2115,96 @@ extern "C" int sv_expect(sv_state s, sv_ising H, double* energy, double* p_gs, d
     return SV_OK;
 }
 
+// Adjoint by two one-vector reverse sweeps.  psi_k and lambda_k = U_{k+1}^+ ... U_p^+ H psi_p
+// are carried back by the same unitaries, so zeta_s = psi + i s t lambda (s = +1, -1) is too,
+// and for a Hermitian A (sum of sigma^x_q, or H_C) expanding the quadratic form gives
+//   <zeta_+|A|zeta_+> - <zeta_-|A|zeta_-> = 4 t Im <lambda|A|psi>,
+// the quantity of the two-vector sweep (df/dbeta_k: A = H_D inside layer k's mixer;
+// df/dgamma_k: A = H_C between the phase and the mixer of layer k).  Each sweep is a chain of
+// one-vector passes (two workgroups per CU) that undoes the layers and accumulates the forms:
+// 2 Re(conj(a) b) per butterfly pair and E |zeta|^2 at the phase.  The forward circuit stops
+// before the last mixer group of layer p; each sweep's first pass applies that group, forms
+// zeta = psi_p (1 + i s t E) pointwise (the zeta_+ pass also reduces norm, <H_C> and P_gs of
+// psi_p) and undoes the group again, so psi_p itself is never stored.  t is fixed before the
+// circuit runs: 1 / sqrt(sum h^2 + sum J^2), the spread of H_C in |+>, which keeps |psi| and
+// t |lambda| of one order.  zeta_+ goes to lam's buffer (its first pass reads psi's), zeta_-
+// then overwrites psi; everything runs on psi's stream.
+static int grad_zeta(sv_state_s* psi, sv_state_s* lam, sv_ising_s* H, int p, const double* gamma,
+                     const double* beta, int psi_is_forward, double* energy, double* p_gs, double* dgamma,
+                     double* dbeta) {
+    Plan plan = make_plan(psi->n, psi->dt);
+    const std::vector<int> order = group_order((int)plan.by_nv[1].size(), (int)psi->dt, psi->n);
+    const bool fuse = knob_for("fuse", (int)psi->dt, psi->n) != 0;
+    double s2 = 0.0;
+    for (double v : H->h) s2 += v * v;
+    for (double v : H->J) s2 += v * v;
+    const double t = s2 > 0.0 ? 1.0 / std::sqrt(s2) : 1.0;
+    // forward circuit without the last mixer group of layer p
+    std::vector<Event> ev;
+    Event last{EV_MIX};
+    if (!psi_is_forward) {
+        forward_events(ev, order, p, gamma, beta, true, -1);
+        last = ev.back();
+        ev.pop_back();
+        if (last.kind != EV_MIX) return fail(SV_ERR_ARG, "internal: forward circuit does not end in a mixer");
+        Program fwd = build_program(ev, 0, fuse);
+        int rc = run_program(psi, nullptr, H, fwd, plan, false);
+        if (rc) return rc;
+    }
+    // the reverse sweep of one zeta: (last group) reductions, zeta, undo layer p .. 1 with the forms
+    auto sweep = [&](double ts, bool reduce) {
+        std::vector<Event> rev;
+        if (!psi_is_forward) rev.push_back(last);
+        if (reduce) {
+            Event r{EV_REDUCE};
+            r.res = 2 * p;
+            rev.push_back(r);
+        }
+        Event z{EV_ZETA};
+        z.angle = ts;
+        rev.push_back(z);
+        for (int k = p - 1; k >= 0; k--) {
+            push_mixer(rev, order, -beta[k], (k % 2) == 0, 1, p + k);
+            Event ef{EV_EFORM};
+            ef.res = k;
+            rev.push_back(ef);
+            if (k > 0) {
+                Event ph{EV_PHASE};
+                ph.angle = -gamma[k];
+                rev.push_back(ph);
+            }
+        }
+        Program prog = build_program(rev, 2 * p + (reduce ? 3 : 0), fuse);
+        prog.passes.back().store = 0;
+        return prog;
+    };
+    Program plus = sweep(t, true);
+    Program minus = sweep(-t, false);
+    const hipStream_t lam_stream = lam->stream;
+    lam->stream = psi->stream;
+    int rc = run_program(lam, nullptr, H, plus, plan, true, nullptr, psi->ptr);
+    lam->stream = lam_stream;
+    if (rc) return rc;
+    rc = run_program(psi, nullptr, H, minus, plan, false);
+    if (rc) return rc;
+    hipError_t e = hipStreamSynchronize(psi->stream);
+    if (e != hipSuccess) {
+        psi->failed = true;
+        return fail(SV_ERR_HIP, "sv_grad: %s", hipGetErrorString(e));
+    }
+    rc = fetch_results(lam, 2 * p + 3);
+    if (rc) return rc;
+    rc = fetch_results(psi, 2 * p);
+    if (rc) return rc;
+    if (energy) *energy = lam->w.h_res[2 * p + 1];
+    if (p_gs) *p_gs = lam->w.h_res[2 * p + 2];
+    for (int k = 0; k < p; k++) {
+        dgamma[k] = (lam->w.h_res[k] - psi->w.h_res[k]) / (2.0 * t);
+        dbeta[k] = (lam->w.h_res[p + k] - psi->w.h_res[p + k]) / (2.0 * t);
+    }
+    return SV_OK;
+}
+
 // Reverse sweep of the adjoint method.  Result layout: [0..2] norm, energy,
 // pgs; [3 + k] = sum E Im(conj lam psi) for gamma_k; [3 + p + k] = pair sums
 // for beta_k.  df/dgamma_k = 2 * res[3+k], df/dbeta_k = 2 * res[3+p+k].
@@ -2106,6 +2221,14 @@ extern "C" int sv_grad(sv_state psi, sv_state lam, sv_ising H, int p, const doub
     rc = check_angles(p, gamma, beta, "sv_grad");
     if (rc) return rc;
     if (lam->failed) return fail(SV_ERR_HIP, "lam state is in a failed state");
+    // the one-vector sweeps run on the default one-vector tiles (13-bit complex128, 14-bit
+    // complex64 with four waves per SIMD)
+    const int dt = (int)psi->dt, nq = psi->n;
+    const bool zeta_tiles = psi->dt == SV_C128 ? knob_for("c128t14", dt, nq) == 0
+                                               : (knob_for("c64t13", dt, nq) == 0 && knob_for("c64occ", dt, nq) != 0);
+    const int zeta = knob_for("adjzeta", dt, nq);
+    if ((zeta > 0 || (zeta < 0 && psi->dt == SV_C128)) && zeta_tiles)
+        return grad_zeta(psi, lam, H, p, gamma, beta, psi_is_forward, energy, p_gs, dgamma, dbeta);
     // both vectors share one tile geometry: plan with the two-vector shape
     Plan plan = make_plan(psi->n, psi->dt, true);
     const std::vector<int> order = group_order((int)plan.by_nv[1].size(), (int)psi->dt, psi->n);

@@ -37,7 +37,9 @@ constexpr int kMaxTR = 16;
 
 enum OpKind : int32_t { OP_MIX = 1, OP_POINT = 2 };
 
-// MIX flags: which vectors get the butterflies; accumulate grad-beta terms.
+// MIX flags: which vectors get the butterflies; accumulate grad-beta terms
+// (two-vector passes: pair sums Im(conj(lam_a) psi_b + conj(lam_b) psi_a);
+// one-vector passes: the quadratic form 2 Re(conj(psi_a) psi_b) of the pair).
 // Every MIX applies (u, v) <- (u - i a v, v - i a u) per active qubit, with
 // a = tan(beta') for |beta'| <= pi/4, and multiplies the vector's uniform
 // pending scale by b = +-cos(beta') per qubit (the host reduces beta modulo pi
@@ -58,7 +60,10 @@ enum PointFlags : int32_t {
     PT_GGAMMA = 4,     // slot2 += E Im(conj(lam) psi)
     PT_PHASE_PSI = 8,  // psi *= exp(-i gamma E)
     PT_PHASE_LAM = 16,  // lam *= exp(-i gamma E); two-vector passes phase both or neither
-    PT_SPINZ = 32       // spin sums: per tile, sum |psi|^2 s_l for every tile bit l and sum |psi|^2
+    PT_SPINZ = 32,      // spin sums: per tile, sum |psi|^2 s_l for every tile bit l and sum |psi|^2
+    PT_E2 = 64,         // slot3 += E^2 |psi|^2 (with PT_REDUCE: the spread of E in the state)
+    PT_ZETA = 128,      // one-vector passes: psi <- psi (1 + i t E), t = Op::b (after the reductions)
+    PT_EFORM = 256      // one-vector passes: slot2 += E |psi|^2
 };
 
 // Per-tile spin partials (PT_SPINZ): kTF doubles per tile, entry l < T =
@@ -77,9 +82,9 @@ struct Op {
     int32_t slot;   // MIX: grad-beta slot; POINT: first reduce slot
     int32_t slot2;  // POINT: grad-gamma slot
     int32_t qidx;   // POINT: index of the (layout, gamma) phase table
-    int32_t pad;
+    int32_t slot3;  // POINT: PT_E2 slot
     double a;       // MIX: tan(beta')   POINT: gamma
-    double b;       // MIX: +-cos(beta')
+    double b;       // MIX: +-cos(beta')   POINT: t of PT_ZETA
 };
 
 // One layout of one tile geometry (device resident, read with uniform loads;
@@ -141,6 +146,7 @@ struct TableJob {
 struct PassArgs {
     void* psi;
     void* lam;
+    const void* src;        // psi is loaded from here when non-null (out-of-place first pass), else from psi
     double* partials;       // [ntiles][nslots]
     const double2* ptab;    // phase tables (k_tables output)
     const GeoBuf* geo;
@@ -168,6 +174,8 @@ struct PassArgs {
     const double* gmat;     // general single-qubit layers (passes whose MIX ops carry MIX_GEN), else null
     int32_t gen_real;       // every general layer of the pass is real
     int32_t kc34;           // two-vector passes with three or four layouts: straight-line kernels
+    int32_t qf;             // one-vector pass of the adjoint sweeps: 1 quadratic forms, 2 also PT_ZETA / PT_EFORM,
+                            // 3 also PT_REDUCE before PT_ZETA
     int32_t occ4;           // complex64 14-bit tiles planned without lane position 4: kernel with
                             // four waves per SIMD (two workgroups per CU)
     uint32_t qph_off[kMaxPhase];

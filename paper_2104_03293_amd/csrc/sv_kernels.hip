@@ -230,7 +230,7 @@ __device__ __forceinline__ double lane_xor(double x) {
 // x <- x - i t x_partner (the same form for the upper and the lower member).
 // With gradient accumulation each lane adds Im(conj(lam_self) psi_partner), so
 // that the pair sum of the register form is split over the two lanes.
-template <int CTRL, typename Real, int R, int NV>
+template <int CTRL, typename Real, int R, int NV, bool QF = false>
 __device__ __forceinline__ void lane_round(Real (&vr)[NV][1 << R], Real (&vi)[NV][1 << R], int flags, Real t,
                                            double cosb, double (&pend)[NV], double& gsum) {
     constexpr int NR = 1 << R;
@@ -257,13 +257,31 @@ __device__ __forceinline__ void lane_round(Real (&vr)[NV][1 << R], Real (&vi)[NV
         }
         pend[v] *= mine ? cosb : 1.0;
     }
+    if constexpr (NV == 1 && QF) {
+        if (flags & MIX_GBETA) {
+            // one-vector quadratic form, taken after the butterfly (which leaves it unchanged)
+            // in a loop of its own: each lane adds Re(conj(self) partner), so the two lanes
+            // of a pair give 2 Re(conj(a) b)
+            double gq[2] = {0.0, 0.0};
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                const Real pr = lane_xor<CTRL>(vr[0][r]), pi = lane_xor<CTRL>(vi[0][r]);
+                gq[r & 1] = fma((double)vr[0][r], (double)pr, gq[r & 1]);
+                gq[r & 1] = fma((double)vi[0][r], (double)pi, gq[r & 1]);
+                // keep the scheduler from hoisting every cross-lane move ahead of the sums
+                // (their results would all be live at once)
+                if ((r & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+            }
+            gsum += (gq[0] + gq[1]) * pend[0] * pend[0];
+        }
+    }
 }
 
 // Butterflies of every active register slot of the current layout; each slot
 // multiplies the pending scale of the touched vectors by cos(beta).  With
 // gradient accumulation the pair terms Im(conj(lam_a) psi_b) + Im(conj(lam_b) psi_a)
 // are taken before each slot's butterfly, weighted by both pending scales.
-template <typename Real, int R, int NV>
+template <typename Real, int R, int NV, bool QF = false>
 __device__ __forceinline__ void mix_round(Real (&vr)[NV][1 << R], Real (&vi)[NV][1 << R], int act, int flags,
                                           Real t, double cosb, double (&pend)[NV], double& gsum) {
     constexpr int NR = 1 << R;
@@ -322,6 +340,28 @@ __device__ __forceinline__ void mix_round(Real (&vr)[NV][1 << R], Real (&vi)[NV]
                 butterfly<Real>(vr[v][r], vi[v][r], vr[v][r2], vi[v][r2], tv);
             }
             pend[v] *= (on && mine) ? cosb : 1.0;
+        }
+    }
+    if constexpr (NV == 1 && QF) {
+        if (flags & MIX_GBETA) {
+            // quadratic forms 2 Re(conj(a) b) of the pairs of every active slot.  A butterfly
+            // on any qubit leaves the form of every other qubit unchanged, so all of them are
+            // taken once, after the round, from the final values and pending scale.
+            double g4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int k = 0; k < R; k++) {
+                if (!((act >> k) & 1)) continue;
+                int j = 0;
+#pragma unroll
+                for (int r = 0; r < NR; r++) {
+                    if (r & (1 << k)) continue;
+                    const int r2 = r | (1 << k);
+                    double& acc = g4[j++ & 3];
+                    acc = fma((double)vr[0][r], (double)vr[0][r2], acc);
+                    acc = fma((double)vi[0][r], (double)vi[0][r2], acc);
+                }
+            }
+            gsum += 2.0 * ((g4[0] + g4[1]) + (g4[2] + g4[3])) * pend[0] * pend[0];
         }
     }
 }
@@ -437,7 +477,7 @@ __global__ void __launch_bounds__(256) k_tables(const TableJobs jobs, double2* _
 // layout walks); KC == 0: generic kernel with a runtime layout count (used for
 // states smaller than one tile and for real-valued instances).
 template <typename Real, int T, int R, int NV, int NS, int MINB, bool PH, bool INTE, int KC, int NTM = 0,
-          bool PERSIST = false, bool SPZ = PH, int GEN = 0>
+          bool PERSIST = false, bool SPZ = PH, int GEN = 0, int QFM = 0>
 __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
     using V2 = typename V2T<Real>::type;
     constexpr int NT = 1 << (T - R);
@@ -496,7 +536,7 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                 vi[0][r] = 0;
             }
         } else if (a.load & 1) {
-            const V2* __restrict__ src = psi + (base | thr_goff);
+            const V2* __restrict__ src = (a.src ? reinterpret_cast<const V2*>(a.src) : psi) + (base | thr_goff);
             if (NTM & 1) {
 #pragma unroll
                 for (int r = 0; r < NR; r++) {
@@ -622,7 +662,7 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                         }
                         return;
                     }
-                    mix_round<Real, R, NV>(vr, vi, act, op.flags, (Real)op.a, op.b, pend, gsum);
+                    mix_round<Real, R, NV, (QFM > 0)>(vr, vi, act, op.flags, (Real)op.a, op.b, pend, gsum);
                     // lane-bit butterflies (one-vector kernels): position 3 (DPP);
                     // position 4 (swizzle) for 14-bit complex64 tiles (a second branch
                     // in the complex128 kernel would exhaust its registers)
@@ -631,18 +671,18 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                         (void)dl;  // two-vector plans butterfly every qubit in registers
                     } else if constexpr (sizeof(Real) == 8) {
                         if (dl != 0)
-                            lane_round<kLaneX8, Real, R, NV>(vr, vi, op.flags, (Real)op.a, op.b, pend, gsum);
+                            lane_round<kLaneX8, Real, R, NV, (QFM > 0)>(vr, vi, op.flags, (Real)op.a, op.b, pend, gsum);
                     } else if constexpr (T == 14 && MINB <= 2) {
                         if (dl & 8)
-                            lane_round<kLaneX8, Real, R, NV>(vr, vi, op.flags, (Real)op.a, op.b, pend, gsum);
+                            lane_round<kLaneX8, Real, R, NV, (QFM > 0)>(vr, vi, op.flags, (Real)op.a, op.b, pend, gsum);
                         else if (dl & 16)
-                            lane_round<kLaneX16, Real, R, NV>(vr, vi, op.flags, (Real)op.a, op.b, pend, gsum);
+                            lane_round<kLaneX16, Real, R, NV, (QFM > 0)>(vr, vi, op.flags, (Real)op.a, op.b, pend, gsum);
                     } else {
                         // 13-bit complex64 tiles, and 14-bit tiles in the four-waves-per-SIMD
                         // kernel (the second branch would not fit its 128 registers), plan lane
                         // position 3 only
                         if (dl != 0)
-                            lane_round<kLaneX8, Real, R, NV>(vr, vi, op.flags, (Real)op.a, op.b, pend, gsum);
+                            lane_round<kLaneX8, Real, R, NV, (QFM > 0)>(vr, vi, op.flags, (Real)op.a, op.b, pend, gsum);
                     }
                 };
                 if constexpr (KC > 0) {
@@ -651,9 +691,7 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                 } else {
                     for (int step = 0; step < K; step++) round(step);
                 }
-                if constexpr (NV == 2) {
-                    if (op.flags & MIX_GBETA) wave_add<NS>(s_red, op.slot, gsum);
-                }
+                if (op.flags & MIX_GBETA) wave_add<NS>(s_red, op.slot, gsum);
             } else {  // OP_POINT
                 // Walk the registers in Gray-code order: consecutive registers differ in
                 // one bit k, so E changes by +-2 f[k] and the phase by exp(-+2i gamma f[k]).
@@ -661,11 +699,70 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                 const double e0 = thread_energy<R, T - R>(L, geo, t, s_g, f);
                 const int fl = op.flags;
                 // E of register r = e0 + (Gray-walk sum of +-2 f[k]) + Q[r]
-                if (fl & (PT_REDUCE | PT_LAM_INIT | PT_GGAMMA | PT_SPINZ)) {
+                if constexpr (QFM >= 2) {
+                    // passes of the adjoint sweeps: zeta = psi (1 + i t E) in the first pass, the
+                    // form sum E |zeta|^2 at the phase of each layer (nothing else is reduced)
+                    // one loop per flag, so that no per-register select keeps the old and the
+                    // new amplitudes alive together.  PT_REDUCE (norm, <H_C>, P_gs of the state
+                    // the sweep starts from) comes before zeta is formed.
+                    if (QFM == 3 && (fl & PT_REDUCE)) {
+                        double r_n = 0.0, r_e = 0.0, r_p = 0.0, e_run = e0;
+#pragma unroll
+                        for (int i = 0; i < NR; i++) {
+                            const int r = i ^ (i >> 1);
+                            if (i > 0) {
+                                const int k = __builtin_ctz(i);
+                                e_run += ((r >> k) & 1) ? 2.0 * f[k] : -2.0 * f[k];
+                            }
+                            const double e = e_run + L->Q[r];
+                            const double pr = (double)vr[0][r], pi = (double)vi[0][r];
+                            const double p2 = fma(pr, pr, pi * pi);
+                            r_n += p2;
+                            r_e = fma(e, p2, r_e);
+                            if (fabs(e - a.emin) <= a.etol) r_p += p2;
+                        }
+                        const double s2 = pend[0] * pend[0];
+                        wave_add<NS>(s_red, op.slot, r_n * s2);
+                        wave_add<NS>(s_red, op.slot + 1, r_e * s2);
+                        wave_add<NS>(s_red, op.slot + 2, r_p * s2);
+                    }
+                    if (fl & PT_ZETA) {
+                        const double zt = op.b;
+                        double e_run = e0;
+#pragma unroll
+                        for (int i = 0; i < NR; i++) {
+                            const int r = i ^ (i >> 1);
+                            if (i > 0) {
+                                const int k = __builtin_ctz(i);
+                                e_run += ((r >> k) & 1) ? 2.0 * f[k] : -2.0 * f[k];
+                            }
+                            const double te = zt * (e_run + L->Q[r]);
+                            const double pr = (double)vr[0][r], pi = (double)vi[0][r];
+                            vr[0][r] = (Real)fma(-te, pi, pr);
+                            vi[0][r] = (Real)fma(te, pr, pi);
+                        }
+                    }
+                    if (fl & PT_EFORM) {
+                        double r_f = 0.0, e_run = e0;
+#pragma unroll
+                        for (int i = 0; i < NR; i++) {
+                            const int r = i ^ (i >> 1);
+                            if (i > 0) {
+                                const int k = __builtin_ctz(i);
+                                e_run += ((r >> k) & 1) ? 2.0 * f[k] : -2.0 * f[k];
+                            }
+                            const double pr = (double)vr[0][r], pi = (double)vi[0][r];
+                            r_f = fma(e_run + L->Q[r], fma(pr, pr, pi * pi), r_f);
+                        }
+                        wave_add<NS>(s_red, op.slot2, r_f * pend[0] * pend[0]);
+                    }
+                }
+                constexpr int kRedFlags = QFM > 0 ? 0 : (PT_REDUCE | PT_LAM_INIT | PT_GGAMMA | PT_SPINZ | PT_E2);
+                if (fl & kRedFlags) {
                     // one sweep over the registers feeds every reduction of the op
                     // (|psi|^2 is formed once; the spin sums of one-vector passes
                     // take it for each register bit k: +-|psi|^2 by bit k of r)
-                    double r_n = 0.0, r_e = 0.0, r_p = 0.0, r_g = 0.0;
+                    double r_n = 0.0, r_e = 0.0, r_p = 0.0, r_g = 0.0, r_e2 = 0.0;
                     double Sk[R];
 #pragma unroll
                     for (int k = 0; k < R; k++) Sk[k] = 0.0;
@@ -681,10 +778,11 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                         }
                         const double e = e_run + L->Q[r];
                         const double pr = (double)vr[0][r], pi = (double)vi[0][r];
-                        if (fl & (PT_REDUCE | PT_SPINZ)) {
+                        if (fl & (PT_REDUCE | PT_SPINZ | PT_E2)) {
                             const double p2 = pr * pr + pi * pi;
                             r_n += p2;
                             r_e += e * p2;
+                            if (fl & PT_E2) r_e2 += e * e * p2;
                             if (fabs(e - a.emin) <= a.etol) r_p += p2;
                             if (spins) {
 #pragma unroll
@@ -708,6 +806,7 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                         wave_add<NS>(s_red, op.slot + 1, r_e * s2);
                         wave_add<NS>(s_red, op.slot + 2, r_p * s2);
                     }
+                    if (fl & PT_E2) wave_add<NS>(s_red, op.slot3, r_e2 * s2);
                     if constexpr (NV == 1 && SPZ) {
                         if (spins) {
                             // tile bit l: register bit k -> Sk[k]; thread bit j -> +-norm
@@ -1083,6 +1182,45 @@ static void launch_gen_fast(const PassArgs& a, dim3 grid, dim3 block, hipStream_
     }
 }
 
+// Passes of the two one-vector adjoint sweeps: QFM = 1 mixer-only passes (quadratic forms),
+// QFM = 2 passes that also form zeta or the E form at their POINT, QFM = 3 the first pass of
+// the zeta_+ sweep, which also reduces norm, <H_C> and P_gs (each part that is not needed
+// is left out: kernels with all of them spill).
+template <typename Real, int T, int R, int NS, int MINB, int QFM>
+static int launch_qf(const PassArgs& a, bool fast, dim3 grid, dim3 block, hipStream_t st) {
+    constexpr int PMB = MINB > 2 ? 2 : MINB;
+    if (!fast && a.lut_half >= 0) {  // states smaller than one tile
+        hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, PMB, true, true, 0, 0, false, false, 0, QFM>), grid, block, 0, st,
+                           a);
+    } else if (!fast) {  // real-valued instances: FP64 sincos
+        hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, 1, true, false, 0, 0, false, false, 0, QFM>), grid, block, 0, st,
+                           a);
+    } else if (a.nlayouts == 1) {
+        hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MINB, false, true, 1, 0, false, false, 0, QFM>), grid, block, 0,
+                           st, a);
+    } else if (a.nlayouts == 2 && a.nt == 3) {
+        hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MINB, false, true, 2, 3, false, false, 0, QFM>), grid, block, 0,
+                           st, a);
+    } else if (a.nlayouts == 2) {
+        hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MINB, false, true, 2, 0, false, false, 0, QFM>), grid, block, 0,
+                           st, a);
+    } else if (sizeof(Real) == 4 && a.nlayouts == 3 && a.nt == 3) {
+        // complex64: straight-line walk (the layout loop spills more there)
+        hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MINB, false, true, 3, 3, false, false, 0, QFM>), grid, block, 0,
+                           st, a);
+    } else if (sizeof(Real) == 4 && a.nlayouts == 3) {
+        hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MINB, false, true, 3, 0, false, false, 0, QFM>), grid, block, 0,
+                           st, a);
+    } else if (a.nt == 3) {
+        hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MINB, false, true, 0, 3, false, false, 0, QFM>), grid, block, 0,
+                           st, a);
+    } else {
+        hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MINB, false, true, 0, 0, false, false, 0, QFM>), grid, block, 0,
+                           st, a);
+    }
+    return (int)hipGetLastError();
+}
+
 // Slot counts: one-vector passes carry up to 8 reduction slots (fused AQA
 // steps); two-vector passes need at most 4 (3 for the turnaround reductions
 // + 1 gradient slot, or 3 gradient slots).
@@ -1113,6 +1251,15 @@ static int run_pass(const PassArgs& a, void* stream) {
         }
     }
     if (a.gmat) return (int)hipErrorInvalidValue;
+    // passes of the two one-vector adjoint sweeps (quadratic forms, zeta, E forms) exist for
+    // the default one-vector tiles: 13-bit complex128 and 14-bit complex64 with four waves per SIMD
+    constexpr bool kQF = NV == 1 && ((sizeof(Real) == 8 && T == 13) || (sizeof(Real) == 4 && T == 14 && MINB == 4));
+    if (a.qf && !kQF) return (int)hipErrorInvalidValue;
+    if constexpr (kQF) {
+        if (a.qf == 1) return launch_qf<Real, T, R, NS, MINB, 1>(a, fast, grid, block, st);
+        if (a.qf == 2) return launch_qf<Real, T, R, NS, MINB, 2>(a, fast, grid, block, st);
+        if (a.qf == 3) return launch_qf<Real, T, R, NS, MINB, 3>(a, fast, grid, block, st);
+    }
     if (fast) {
         // one or two layouts: straight-line walks; three or more: a loop keeps
         // the register pressure below the two-workgroups-per-CU limit

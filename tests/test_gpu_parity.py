@@ -401,6 +401,41 @@ def test_grad_vs_oracle(sv, orc, dtype, n, p):
     assert np.max(np.abs(db - rb)) <= GRAD_TOL[dtype] * scale
 
 
+@pytest.mark.parametrize("zeta", [0, 1])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,kind", [(5, "real"), (14, "int"), (21, "real"), (26, "int")])
+def test_grad_both_reverse_sweeps(sv, orc, record_error, dtype, n, kind, zeta):
+    """Both adjoint schemes against the oracle's forward-mode gradient, from |+> and
+    from a given forward state: one sweep of psi and lambda in two-vector passes
+    (knob adjzeta = 0), and two one-vector sweeps of psi +- i t lambda whose
+    quadratic forms differ by 4 t Im <lambda|A|psi> (adjzeta = 1); n = 26 has three
+    tile groups, n = 5 is smaller than one tile."""
+    p = 3
+    inst = instance_for(n, kind, 700 + n)
+    H = sv.Ising.from_instance(inst)
+    g, b = I.uniform_params(p, 701 + n, -1.1, 1.1)
+    f, rg, rb = orc.grad_tangent(inst, g, b)
+    _, _, rpg = orc.observables(inst, orc.qaoa_state(inst, g, b))
+    scale = max(np.max(np.abs(np.concatenate([rg, rb]))), orc.coeff_scale(inst))
+    old = sv.tune_get("adjzeta")
+    sv.tune_set("adjzeta", zeta)
+    try:
+        for from_state in (False, True):
+            psi = sv.State(n, dtype)
+            lam = sv.State(n, dtype)
+            if from_state:
+                sv.qaoa_forward(psi, H, g, b)
+            e, pg, dg, db = sv.grad(psi, lam, H, g, b, psi_is_forward=from_state, with_pgs=True)
+            err = max(np.max(np.abs(dg - rg)), np.max(np.abs(db - rb))) / scale
+            record_error(f"grad / scale {dtype} adjzeta={zeta}", err)
+            assert abs(e - f) <= energy_tol(orc, inst, f)
+            assert abs(pg - rpg) <= PROB_TOL[dtype]
+            assert err <= GRAD_TOL[dtype], (from_state, err)
+            del psi, lam
+    finally:
+        sv.tune_set("adjzeta", old)
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_grad_from_forward_state(sv, orc, dtype):
     n, p = 17, 3
