@@ -571,3 +571,41 @@ def test_gradient_tangent_p8_vs_dense_fd(orc, p):
     scale = max(1.0, orc.coeff_scale(inst))
     assert np.max(np.abs(dg - fg)) < 1e-8 * scale
     assert np.max(np.abs(db - fb)) < 1e-8 * scale
+
+
+# ----------------------------------------------------------------------------- two-sweep adjoint identity
+@pytest.mark.parametrize("t_scale", [1.0, 0.1, 10.0])
+@pytest.mark.parametrize("p", [1, 3])
+def test_two_sweep_adjoint_identity(orc, p, t_scale):
+    """The identity behind the library's one-vector adjoint sweeps, with oracle
+    primitives only: psi_k and lambda_k = U_{k+1}^+ .. U_p^+ H psi_p are carried
+    back by the same unitaries, so zeta_s = psi_p (1 + i s t E) (s = +-1) reversed
+    layer by layer gives, for A = sum_q sigma^x_q inside layer k's mixer and A = H_C
+    between its phase and mixer,
+        (<zeta_+|A|zeta_+> - <zeta_-|A|zeta_->) / (2 t) = df/dbeta_k, df/dgamma_k,
+    for any t > 0.  Checked against the forward-mode tangents; a dropped factor
+    (t, 2, the 1/2 of the pair form) or a sign would fail it."""
+    n = 8
+    inst = I.degree4_int2(n, 30 + p)
+    E = orc.energies(inst)
+    g, b = I.uniform_params(p, 31 + p, -1.2, 1.2)
+    psi = orc.qaoa_state(inst, g, b, E=E)
+    _, rg, rb = orc.grad_tangent(inst, g, b, E=E)
+    t = t_scale / math.sqrt(float(np.sum(np.asarray(inst["h"]) ** 2) + np.sum(np.asarray(inst["J"]) ** 2)))
+    idx = np.arange(1 << n)
+
+    def sweep(s):
+        z = psi * (1.0 + 1j * s * t * E)
+        Rg, Rb = np.zeros(p), np.zeros(p)
+        for k in range(p - 1, -1, -1):
+            Rb[k] = sum(np.real(np.vdot(z, z[idx ^ (1 << q)])) for q in range(n))
+            z = orc.mixer(n, z, -b[k])
+            Rg[k] = float(np.sum(E * np.abs(z) ** 2))
+            z = orc.cost_phase(inst, z, -g[k], E=E)
+        return Rg, Rb
+
+    Rgp, Rbp = sweep(+1)
+    Rgm, Rbm = sweep(-1)
+    scale = max(float(np.max(np.abs(np.concatenate([rg, rb])))), 1.0)
+    assert np.max(np.abs((Rgp - Rgm) / (2 * t) - rg)) <= 1e-12 * scale
+    assert np.max(np.abs((Rbp - Rbm) / (2 * t) - rb)) <= 1e-12 * scale
