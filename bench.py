@@ -50,6 +50,9 @@ def main():
     ap.add_argument("--cpu-sample-p", type=int, default=4)
     ap.add_argument("--knob", action="append", default=[], metavar="NAME=VALUE",
                     help="set a plan knob of the library before the run (repeatable)")
+    ap.add_argument("--tune-cache", default="",
+                    help="autotuner cache to load (default: paper_2104_03293_amd/tune_cache.txt if present; "
+                         "'none' for the built-in defaults)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="run one plain device-to-device copy of this size first (counter reference)")
     args = ap.parse_args()
@@ -64,6 +67,11 @@ def main():
     from paper_2104_03293_amd import sv
 
     torch.cuda.set_device(0)
+    # the autotuner's choices (committed cache of tune.py), unless another is named
+    cache = Path(args.tune_cache) if args.tune_cache else ROOT / "paper_2104_03293_amd" / "tune_cache.txt"
+    if args.tune_cache != "none" and cache.exists():
+        sv.tune_load(str(cache))
+        log(f"[bench] tuned knobs from {cache.name}")
     for kv in args.knob:
         name, val = kv.split("=")
         sv.tune_set(name, int(val))
@@ -328,6 +336,7 @@ def main():
         "config": {"workload": f"QAOA p={p} energy evaluation (forward + fused <H_C>/P_gs), n={n} {args.dtype}, random Ising G(n,2n) "
                                f"J in [-2,2], h in {{-1,0,1}}", "n": n, "p": p, "amp_dtype": args.dtype},
         "roofline": roof,
+        "tuned": tuned_knobs(sv, args.dtype, n),
         "cpu_baseline": cpu,
         "extras": extras,
     }
@@ -394,6 +403,12 @@ def full_size_leg(sv, I, n: int, dtype: str, p: int) -> dict:
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
     return res
+
+
+def tuned_knobs(sv, dtype: str, n: int) -> dict:
+    """Plan knobs in effect for (dtype, n): the tuned overrides where the cache has them."""
+    d = sv.describe(n, dtype)
+    return d.get("knobs_for_size", {})
 
 
 def stream_ceilings(sv, s, n: int, dtype: str) -> dict:

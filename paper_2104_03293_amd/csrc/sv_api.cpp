@@ -2375,6 +2375,21 @@ extern "C" int sv_tune_describe(int n, sv_dtype dtype, char* buf, size_t len) {
             first = false;
         }
     }
+    js += "},\"knobs_for_size\":{";
+    {
+        std::vector<std::string> names;
+        {
+            std::lock_guard<std::mutex> g(g_knob_mu);
+            for (auto& kv : g_knobs) names.push_back(kv.first);
+        }
+        bool first = true;
+        for (const std::string& k : names) {
+            // the values a plan for this (dtype, n) uses: tuned overrides over the global knobs
+            const int nsz = (k == "batchwide" || k == "batch128") ? 0 : n;
+            js += (first ? "" : ",") + std::string("\"") + k + "\":" + std::to_string(knob_for(k.c_str(), (int)dtype, nsz));
+            first = false;
+        }
+    }
     js += "},\"plans\":{";
     for (int fam = 0; fam < 3; fam++) {
         const int nv = fam == 2 ? 2 : 1;
