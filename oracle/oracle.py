@@ -31,7 +31,9 @@ _ip = ctypes.POINTER(ctypes.c_int32)
 _u64p = ctypes.POINTER(ctypes.c_uint64)
 
 
-_LIB_PATH = None  # another compiled copy of oracle.c (use_library), else oracle/liboracle.so
+# another compiled copy of oracle.c (use_library, or $ORACLE_LIBRARY: the
+# sanitized build of build.py), else oracle/liboracle.so
+_LIB_PATH = Path(os.environ["ORACLE_LIBRARY"]).resolve() if os.environ.get("ORACLE_LIBRARY") else None
 
 
 def use_library(path) -> None:

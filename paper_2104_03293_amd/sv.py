@@ -8,13 +8,16 @@ from __future__ import annotations
 
 import ctypes
 import json
+import os
 from pathlib import Path
 from typing import Optional, Sequence
 
 import numpy as np
 
 _HERE = Path(__file__).resolve().parent
-LIB_PATH = _HERE / "libsv.so"
+# SV_LIBRARY names another build of the same sources (the sanitized host build
+# libsv_san.so of build.py); default: the in-tree libsv.so
+LIB_PATH = Path(os.environ["SV_LIBRARY"]).resolve() if os.environ.get("SV_LIBRARY") else _HERE / "libsv.so"
 
 SV_C64, SV_C128 = 1, 2
 _CODES = {0: "ok", 1: "bad argument", 2: "out of memory", 3: "HIP error", 4: "unsupported", 5: "non-finite value"}
