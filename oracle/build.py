@@ -30,13 +30,13 @@ def build(verbose: bool = False, out: Path | None = None, native: bool = False) 
     return out
 
 
-def build_sanitized(verbose: bool = False) -> Path:
+def build_sanitized(verbose: bool = False, out: Path | None = None) -> Path:
     """oracle/liboracle_san.so: oracle.c under ASan + UBSan, built with the ROCm
     clang so that one shared sanitizer runtime serves it and the sanitized host
     library of the product (paper_2104_03293_amd/build.py, build_sanitized) in
     the same Python process."""
     src = HERE / "oracle.c"
-    out = HERE / "liboracle_san.so"
+    out = Path(out) if out is not None else HERE / "liboracle_san.so"
     tmp = out.with_name(out.name + ".tmp")
     llvm = Path(os.environ.get("SV_CLANG_DIR", "/opt/rocm/llvm/bin"))
     cmd = [str(llvm / "clang"), "-O1", "-g", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math",

@@ -62,7 +62,7 @@ def build(verbose: bool = False) -> Path:
     return LIB
 
 
-def build_sanitized(verbose: bool = False) -> Path:
+def build_sanitized(verbose: bool = False, out: Path | None = None) -> Path:
     """libsv_san.so: the same library with its host code (planner, program
     builder, entry points, argument checks) under ASan + UBSan, for the CPU
     tests.  The kernels object is the one of the normal build; the library is
@@ -83,15 +83,16 @@ def build_sanitized(verbose: bool = False) -> Path:
     with ThreadPoolExecutor(max_workers=len(srcs)) as ex:
         list(ex.map(lambda so: _compile(so[0], so[1], verbose, HOST_SAN_FLAGS), zip(srcs, objs)))
     rocm = Path(os.environ.get("ROCM_PATH", "/opt/rocm"))
-    tmp = HERE / "libsv_san.so.tmp"
+    out = Path(out) if out is not None else LIB_SAN
+    tmp = out.with_name(out.name + ".tmp")
     san = ",".join(_SAN)
     cmd = [str(CLANG_DIR / "clang++"), "-shared", "-fPIC", f"-fsanitize={san}", "-shared-libsan", "-o", str(tmp),
            str(kobj), *map(str, objs), f"-L{rocm / 'lib'}", "-lamdhip64", f"-Wl,-rpath,{rocm / 'lib'}"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    tmp.replace(LIB_SAN)
-    return LIB_SAN
+    tmp.replace(out)
+    return out
 
 
 if __name__ == "__main__":

@@ -26,6 +26,7 @@ gradients GRAD_TOL * max(max|g|, sum|h| + sum|J|).  The achieved errors are
 recorded (printed per case and summarised at the end of the run).
 """
 import sys
+from pathlib import Path
 
 import numpy as np
 import pytest
@@ -226,6 +227,17 @@ def test_grad_p8_n20_vs_oracle_central_differences(sv, orc, record_error):
 
 # ----------------------------------------------------------------------------- full size, coupled instances
 FULL = [("c128", 32), ("c64", 32), ("c128", 33), ("c64", 34)]
+TUNE_CACHE = Path(__file__).resolve().parents[1] / "paper_2104_03293_amd" / "tune_cache.txt"
+
+
+@pytest.fixture
+def bench_plan(sv):
+    """The plan knobs the benchmark runs with: the committed autotuner cache
+    (when present) on top of the built-in defaults."""
+    if TUNE_CACHE.exists():
+        sv.tune_load(str(TUNE_CACHE))
+    yield
+    sv.tune_load(None)
 
 
 def sample_indices(n, count, seed):
@@ -241,7 +253,7 @@ def gather(s, zs):
 
 
 @pytest.mark.parametrize("dtype,n", FULL)
-def test_block_instance_full_size_state(sv, orc, record_error, dtype, n):
+def test_block_instance_full_size_state(sv, orc, record_error, bench_plan, dtype, n):
     """p = 4 energy evaluation in the benchmark's tile geometry: 8192 sampled
     amplitudes, <H_C> and P_gs against the tensor product of the cliques' states."""
     elem = 16 if dtype == "c128" else 8
@@ -266,7 +278,7 @@ def test_block_instance_full_size_state(sv, orc, record_error, dtype, n):
 
 
 @pytest.mark.parametrize("dtype,n", FULL)
-def test_block_instance_full_size_gradient(sv, orc, record_error, dtype, n):
+def test_block_instance_full_size_gradient(sv, orc, record_error, bench_plan, dtype, n):
     """Adjoint gradient (p = 4, 8 parameters) at full size with couplings: the sum
     of the cliques' forward-mode gradients."""
     elem = 16 if dtype == "c128" else 8
@@ -291,7 +303,7 @@ def test_block_instance_full_size_gradient(sv, orc, record_error, dtype, n):
 
 
 @pytest.mark.parametrize("dtype,n", FULL)
-def test_block_instance_full_size_annealing(sv, orc, record_error, dtype, n):
+def test_block_instance_full_size_annealing(sv, orc, record_error, bench_plan, dtype, n):
     """Ten coarse annealing steps: per-step <H_C> and P_gs, and the final
     <sigma^z_i>, against the cliques' step-by-step states."""
     elem = 16 if dtype == "c128" else 8
@@ -347,6 +359,43 @@ def test_xcd_tile_orders_agree(sv, orc, record_error, dtype, n):
         assert o[4] == ref[4] and np.array_equal(o[5], ref[5]) and np.array_equal(o[6], ref[6]), x
     E = orc.energies(inst)
     rpsi = orc.qaoa_state(inst, g, b, E=E)
+    err = float(np.max(np.abs(ref[3] - rpsi)))
+    record_error(f"amp max-abs {dtype}", err)
+    assert err <= AMP_TOL[dtype]
+    _, rg, rb = orc.grad_tangent(inst, g, b)
+    scale = grad_scale(orc, inst, rg, rb)
+    gerr = max(np.max(np.abs(ref[5] - rg)), np.max(np.abs(ref[6] - rb))) / scale
+    record_error(f"grad / scale {dtype}", gerr)
+    assert gerr <= GRAD_TOL[dtype]
+
+
+@pytest.mark.parametrize("dtype,n", [("c128", 26), ("c64", 26)])
+def test_lds_swizzle_and_nontemporal_agree(sv, orc, record_error, dtype, n):
+    """The LDS slot swizzle width (knob ldsswz = 3, 4, 5) only moves where a
+    tile's amplitudes sit in LDS during an exchange, and the nontemporal
+    threshold (ntmin = 0: every pass, 64: none) only changes cache hints: the
+    state, the observables and the adjoint gradient are bit-identical, and they
+    match the oracle."""
+    inst = I.degree4_int2(n, 680 + n)
+    H = sv.Ising.from_instance(inst)
+    g, b = I.uniform_params(3, 681 + n, -1.1, 1.1)
+    out = {}
+    for knob, vals in (("ldsswz", (3, 4, 5)), ("ntmin", (0, 4, 64))):
+        for v in vals:
+            with Knob(sv, knob, v):
+                s = sv.State(n, dtype)
+                lam = sv.State(n, dtype)
+                e, pg, nrm = sv.qaoa_energy(s, H, g, b)
+                psi = s.to_numpy()
+                ge, dg, db = sv.grad(s, lam, H, g, b)
+                out[(knob, v)] = (e, pg, nrm, psi, ge, dg, db)
+                del s, lam
+    ref = out[("ldsswz", 4)]
+    for k, o in out.items():
+        assert o[:3] == ref[:3], (k, o[:3], ref[:3])
+        assert np.array_equal(o[3], ref[3]), k
+        assert o[4] == ref[4] and np.array_equal(o[5], ref[5]) and np.array_equal(o[6], ref[6]), k
+    rpsi = orc.qaoa_state(inst, g, b, E=orc.energies(inst))
     err = float(np.max(np.abs(ref[3] - rpsi)))
     record_error(f"amp max-abs {dtype}", err)
     assert err <= AMP_TOL[dtype]

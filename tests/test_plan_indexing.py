@@ -64,11 +64,16 @@ def replay(n, g, G):
         assert np.array_equal(np.sort(z), np.arange(1 << n, dtype=np.uint64))
 
 
+# LDS swizzle widths the library accepts (knob ldsswz): the default 4 at every
+# size, 3 and 5 at sizes that cover one, two and three tile groups
+BIJECTION_CASES = [(n, 4) for n in (1, 2, 4, 7, 9, 12, 13, 14, 15, 16, 19, 21, 24)] + [
+    (n, G) for n in (7, 14, 16, 21) for G in (3, 5)]
+
+
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("n", [1, 2, 4, 7, 9, 12, 13, 14, 15, 16, 19, 21, 24])
-def test_every_layout_is_a_bijection(sv, dtype, n):
+@pytest.mark.parametrize("n,G", BIJECTION_CASES)
+def test_every_layout_is_a_bijection(sv, dtype, n, G):
     d = sv.describe(n, dtype)
-    G = 4  # LDS swizzle width of the tile passes
     for key in ("nv1", "grad_nv1", "grad_nv2"):
         for g in d["plans"][key]:
             replay(n, g, G)

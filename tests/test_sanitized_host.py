@@ -26,8 +26,8 @@ def test_cpu_suite_under_asan_ubsan(tmp_path):
     clang = pbuild.CLANG_DIR / "clang"
     if not clang.exists():
         pytest.skip(f"{clang} not found")
-    svlib = pbuild.build_sanitized()
-    olib = obuild.build_sanitized()
+    svlib = pbuild.build_sanitized(out=tmp_path / "libsv_san.so")
+    olib = obuild.build_sanitized(out=tmp_path / "liboracle_san.so")
     rt = subprocess.run([str(clang), "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True,
                         text=True, check=True).stdout.strip()
     assert Path(rt).exists(), rt
