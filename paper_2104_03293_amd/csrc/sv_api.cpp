@@ -67,6 +67,8 @@ std::map<std::string, int> g_knobs = {
     {"c64g4", 1},     // complex64 two-vector passes: 1 = four waves per SIMD (two workgroups per CU)
     {"kc34", 1},      // two-vector passes with 3 or 4 layouts: 1 = straight-line kernels, 0 = layout loop
     {"c64g14", 2},    // complex64 adjoint programs on 14-bit tiles: 1 always, 2 when fewer groups, 0 never
+    {"batchslab", 256},  // batch scan, states above the LDS tile: MiB of the cache-resident slab of one
+                         // sliced launch (0: per-workgroup slots in device memory)
     {"ntinit", 1},    // write-only first passes: 1 = nontemporal stores
     {"split", 0},     // bits above the contiguous tile: 0 = near-equal groups, 1 = largest groups first
     {"xcd", -1},      // x > 0: XCD-aware tile order, 8 * 2^(x-1) interleaved streams of contiguous tiles;
@@ -85,7 +87,7 @@ const std::map<std::string, std::pair<int, int>> g_knob_range = {
     {"fuse", {0, 1}},    {"cmin64", {0, 8}},   {"cmin128", {0, 8}},  {"ntmin", {0, 64}},   {"persist", {0, 8}},
     {"stagger", {0, 64}}, {"snake", {0, 2}},   {"dpp", {0, 1}},      {"ldsswz", {3, 5}},   {"batchwide", {0, 2}},
     {"batch128", {0, 1}}, {"c64t13", {0, 1}},  {"c64occ", {0, 1}},   {"c64g4", {0, 1}},    {"kc34", {0, 1}},
-    {"c64g14", {0, 2}},  {"ntinit", {0, 1}},   {"split", {0, 1}},    {"xcd", {-1, 5}},      {"c128t14", {0, 1}}, {"adjzeta", {-1, 1}},
+    {"c64g14", {0, 2}},  {"ntinit", {0, 1}},   {"batchslab", {0, 4096}},   {"split", {0, 1}},    {"xcd", {-1, 5}},      {"c128t14", {0, 1}}, {"adjzeta", {-1, 1}},
     {"fail_next_launch", {0, 1}},
 };
 int knob(const char* k) {
@@ -2385,7 +2387,7 @@ extern "C" int sv_tune_describe(int n, sv_dtype dtype, char* buf, size_t len) {
         bool first = true;
         for (const std::string& k : names) {
             // the values a plan for this (dtype, n) uses: tuned overrides over the global knobs
-            const int nsz = (k == "batchwide" || k == "batch128") ? 0 : n;
+            const int nsz = (k == "batchwide" || k == "batch128" || k == "batchslab") ? 0 : n;
             js += (first ? "" : ",") + std::string("\"") + k + "\":" + std::to_string(knob_for(k.c_str(), (int)dtype, nsz));
             first = false;
         }
@@ -2484,15 +2486,29 @@ extern "C" int sv_batch_p1_scan(int n_inst, const sv_ising* insts, int n_gamma, 
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) dev = 0;
     const int grid = device_cu_count(dev) * (wide == 2 ? 2 : 1);
-    const uint64_t slot = max_n > S ? (1ull << max_n) : 0;
+    // states above the LDS tile: the sliced path (slab launches) where the variant has
+    // 13-bit LDS states, else per-workgroup slots of the persistent kernel
+    const int slab_mb = knob_for("batchslab", (int)dtype, 0);
+    const bool sliced = slab_mb > 0 && S == 13 && max_n > S;
+    const uint64_t slot = (max_n > S && !sliced) ? (1ull << max_n) : 0;
+    const size_t slab_bytes = sliced ? std::max((size_t)slab_mb << 20, (size_t(1) << max_n) * elem_size(dtype)) : 0;
+    auto states_per_launch = [&](int n) -> int64_t {
+        return std::max<int64_t>(1, (int64_t)(slab_bytes / ((size_t(1) << n) * elem_size(dtype))));
+    };
+    size_t part_doubles = 0;
+    if (sliced)
+        for (int n = S + 1; n <= max_n; n++)
+            part_doubles = std::max(part_doubles, (size_t)states_per_launch(n) * 2 << (n - S));
     const size_t nout = (size_t)n_inst * n_gamma * n_beta;
     hipStream_t st = (hipStream_t)stream;
     // device buffers
     std::vector<void*> bufs;
+    bool oom = false;
     auto dalloc = [&](size_t bytes) -> void* {
         void* p = nullptr;
         if (hipMalloc(&p, std::max<size_t>(bytes, 16)) != hipSuccess) {
             (void)hipGetLastError();
+            oom = true;
             return nullptr;
         }
         bufs.push_back(p);
@@ -2519,11 +2535,14 @@ extern "C" int sv_batch_p1_scan(int n_inst, const sv_ising* insts, int n_gamma, 
     double* d_op = (double*)dalloc(nout * sizeof(double));
     unsigned* d_cnt = (unsigned*)dalloc(sizeof(unsigned));
     void* d_scr = dalloc(slot * grid * elem);
-    for (void* p : bufs)
-        if (!p) {
-            cleanup();
-            return fail(SV_ERR_OOM, "sv_batch_p1_scan: device allocation failed");
-        }
+    void* d_slab = sliced ? dalloc(slab_bytes) : nullptr;
+    // partial sums, two buffers: a launch's columns fill one while its slice kernel
+    // finishes the previous launch's states from the other
+    double* d_part = sliced ? (double*)dalloc(2 * part_doubles * sizeof(double)) : nullptr;
+    if (oom) {
+        cleanup();
+        return fail(SV_ERR_OOM, "sv_batch_p1_scan: device allocation failed");
+    }
     hipError_t e = hipSuccess;
     auto up = [&](void* d, const void* h, size_t bytes) {
         if (e == hipSuccess && bytes) e = hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, st);
@@ -2563,7 +2582,57 @@ extern "C" int sv_batch_p1_scan(int n_inst, const sv_ising* insts, int n_gamma, 
     if (e == hipSuccess && !ke) {
         hipEvent_t ev0;
         const bool prof = prof_begin(st, &ev0);
-        ke = launch_batch_scan((int)dtype, ba, grid, wide, st);
+        if (!sliced) {
+            ke = launch_batch_scan((int)dtype, ba, grid, wide, st);
+        } else {
+            // units are sorted by n, largest first: those with n <= S take the persistent
+            // kernel, the others go through slab launches of one n each
+            size_t first_small = 0;
+            while (first_small < uinst.size() && bi[uinst[first_small]].n > S) first_small++;
+            if (first_small < uinst.size()) {
+                BatchArgs bs = ba;
+                bs.unit_inst = d_ui + first_small;
+                bs.unit_gam = d_ug + first_small;
+                bs.nunits = (int32_t)(uinst.size() - first_small);
+                ke = launch_batch_scan((int)dtype, bs, grid, wide, st);
+            }
+            BatchArgs prev = ba;  // the launch whose states are still to be finished
+            prev.s_count = 0;
+            int nlaunch = 0;
+            auto finish_of = [&](BatchArgs& bs) {
+                bs.f_n = prev.s_n;
+                bs.f_u0 = prev.s_u0;
+                bs.f_base = prev.s_base;
+                bs.f_count = prev.s_count;
+                bs.f_part = prev.part;
+            };
+            for (size_t u0 = 0; u0 < first_small && !ke;) {
+                const int n = bi[uinst[u0]].n;
+                size_t u1 = u0;
+                while (u1 < first_small && bi[uinst[u1]].n == n) u1++;
+                const int64_t states = (int64_t)(u1 - u0) * n_beta;
+                const int64_t per = states_per_launch(n);
+                for (int64_t s0 = 0; s0 < states && !ke; s0 += per) {
+                    BatchArgs bs = ba;
+                    bs.s_n = n;
+                    bs.s_u0 = (int32_t)u0;
+                    bs.s_base = s0;
+                    bs.s_count = (int32_t)std::min(per, states - s0);
+                    bs.slab = d_slab;
+                    bs.part = d_part + (nlaunch & 1) * part_doubles;
+                    finish_of(bs);
+                    ke = launch_batch_sliced((int)dtype, bs, wide, st);
+                    prev = bs;
+                    nlaunch++;
+                }
+                u0 = u1;
+            }
+            if (!ke && prev.s_count > 0) {
+                BatchArgs bs = ba;
+                finish_of(bs);
+                ke = launch_batch_finish(bs, st);
+            }
+        }
         if (prof) prof_end(st, ev0, std::string("batch_") + (dtype == SV_C128 ? "c128" : "c64"), 0.0);
     }
     if (e == hipSuccess && !ke) e = hipMemcpyAsync(energy_out, d_oe, nout * sizeof(double), hipMemcpyDeviceToHost, st);

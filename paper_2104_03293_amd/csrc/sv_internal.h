@@ -259,10 +259,28 @@ struct BatchArgs {
     unsigned int* counter;  // work-queue head (zeroed before the launch)
     void* scratch;          // per-workgroup slices for states larger than LDS
     uint64_t scratch_elems; // elements per workgroup slot
+    // sliced path (states with n > S, a launch at a time): state s of a launch is
+    // the group state g = s_base + s, i.e. unit s_u0 + g / nb and beta index g % nb
+    int32_t s_n;            // qubits of every state of the launch
+    int32_t s_u0;           // first unit of the n-group
+    int64_t s_base;         // first group state of the launch
+    int32_t s_count;        // states in the launch
+    void* slab;             // s_count x 2^s_n amplitudes
+    double* part;           // s_count x 2^(s_n - S) x 2 partial sums
+    // the previous launch, whose states the slice kernel of this one finishes
+    // (f_count = 0: none)
+    int32_t f_n, f_u0, f_count;
+    int64_t f_base;
+    const double* f_part;
 };
 
 int launch_batch_energy(const BatchArgs& a, int max_n, void* stream);
 int launch_batch_scan(int dtype, const BatchArgs& a, int grid, int wide, void* stream);
+// Sliced path for states larger than the LDS tile: slices (which also finish
+// the previous launch's states, a.f_*) and columns of one launch (a.s_*,
+// a.slab, a.part); launch_batch_finish finishes the last launch's states.
+int launch_batch_sliced(int dtype, const BatchArgs& a, int wide, void* stream);
+int launch_batch_finish(const BatchArgs& a, void* stream);
 int batch_lds_bits(int dtype, int wide);  // log2 of the LDS-resident state of a batch variant
 int batch_lut_cap(int dtype, int wide);   // phase-table entries of a batch variant
 

@@ -1868,6 +1868,270 @@ int launch_batch_energy(const BatchArgs& a, int max_n, void* stream) {
     return (int)hipGetLastError();
 }
 
+// ---------------------------------------------------------------- sliced states
+// States larger than the LDS tile (n > S) go through a slab of a few hundred MB
+// that stays in the last-level cache between two kernels, instead of a
+// per-workgroup slot of 2^n amplitudes that streams through HBM:
+//   k_batch_slices  one workgroup per (state, slice of 2^S amplitudes): phase
+//                   state of the slice, mixer on the low S bits, slice -> slab;
+//   k_batch_columns one workgroup per (state, block of 2^S amplitudes taken as
+//                   2^(S - nh) columns of the 2^nh high-bit values): mixer on
+//                   the high bits, <H_C> and P_gs partial sums;
+//   k_batch_finish  one thread per state: its partials in a fixed order, times
+//                   the deferred cos(beta)^{2n}.
+// Mixer in the tangent form on |beta| <= pi/4 as in k_batch_scan; fl flips the
+// table index where beta was moved by pi/2.
+__device__ __forceinline__ double batch_reduce_beta(double beta, int n, uint32_t& fl) {
+    double bb = remainder(beta, M_PI);
+    fl = 0u;
+    if (fabs(bb) > 0.25 * M_PI) {
+        bb -= copysign(0.5 * M_PI, bb);
+        fl = (uint32_t)((1ull << n) - 1ull);
+    }
+    return bb;
+}
+
+// <H_C> and P_gs of state s of a launch (qubits n, first unit u0, first group
+// state base): its 2^(n - S) partial sums in a fixed order, times cos(beta)^{2n}.
+__device__ void batch_finish_state(const BatchArgs& a, int S, int n, int u0, int64_t base, const double* part,
+                                   int s) {
+    const int nh = n - S;
+    const int64_t g = base + s;
+    const int u = u0 + (int)(g / a.nb);
+    const int b = (int)(g % a.nb);
+    uint32_t fl;
+    const double bb = batch_reduce_beta(a.betas[b], n, fl);
+    double se = 0.0, sp = 0.0;
+    const double* P = part + ((uint64_t)s << nh) * 2;
+    for (int k = 0; k < (1 << nh); k++) {
+        se += P[2 * k];
+        sp += P[2 * k + 1];
+    }
+    const double cb = cos(bb), sc = pow(cb * cb, (double)n);  // the deferred cos(beta)^{2n}
+    const uint64_t o = ((uint64_t)a.unit_inst[u] * a.ng + a.unit_gam[u]) * a.nb + b;
+    a.out_e[o] = se * sc;
+    a.out_p[o] = sp * sc;
+}
+
+template <typename Real, int NTH, int S, int LUTN, int MINW>
+__global__ void __launch_bounds__(NTH, MINW) k_batch_slices(const BatchArgs a) {
+    using V2 = typename V2T<Real>::type;
+    constexpr int G = BatchCfg<Real>::G;
+    constexpr int U = kBatchUnroll;
+    constexpr int LB = S - 5;
+    constexpr int MB = S - 10;
+    static_assert(S >= 10 && S <= 15, "slice rounds assume 10 <= S <= 15");
+    __shared__ V2 st[1 << S];
+    __shared__ V2 lut[LUTN];  // 2^{-n/2} exp(-i gamma E), rounded once to the storage type
+    const int t = threadIdx.x;
+    const int n = a.s_n;
+    const int nh = n - S;
+    const uint32_t nsl = (uint32_t)a.s_count << nh;
+    if (blockIdx.x >= nsl) {  // trailing workgroups: the previous launch's states
+        const int fs = (int)(blockIdx.x - nsl) * NTH + t;
+        if (fs < a.f_count) batch_finish_state(a, S, a.f_n, a.f_u0, a.f_base, a.f_part, fs);
+        return;
+    }
+    const uint32_t s = blockIdx.x >> nh;
+    const uint32_t sl = blockIdx.x & ((1u << nh) - 1u);
+    const int64_t g = a.s_base + s;
+    const int u = a.s_u0 + (int)(g / a.nb);
+    const int b = (int)(g % a.nb);
+    const BatchInst in = a.inst[a.unit_inst[u]];
+    const double gam = a.gammas[a.unit_gam[u]];
+    const double amp0 = exp2(-0.5 * n);
+    const bool intE = in.lut_n > 0;
+    uint32_t fl;
+    const Real tq = (Real)tan(batch_reduce_beta(a.betas[b], n, fl));
+    const uint64_t off = in.eoff + ((uint64_t)sl << S);
+    V2* __restrict__ Ss = reinterpret_cast<V2*>(a.slab) + ((uint64_t)s << n) + ((uint64_t)sl << S);
+    if (intE) {
+        for (int m = t; m < in.lut_n; m += NTH) {
+            double sn, cs;
+            sincos(gam * (double)(in.lut_lo + m), &sn, &cs);
+            lut[m].x = (Real)(amp0 * cs);
+            lut[m].y = (Real)(-amp0 * sn);
+        }
+    } else {
+        const double* E = a.etab + off;
+        for (uint32_t z0 = t; z0 < (1u << S); z0 += NTH * U) {
+            double e[U];
+#pragma unroll
+            for (int j = 0; j < U; j++) e[j] = E[z0 + j * NTH];
+#pragma unroll 1
+            for (int j = 0; j < U; j++) {
+                double sn, cs;
+                sincos(gam * e[j], &sn, &cs);
+                V2 v;
+                v.x = (Real)(amp0 * cs);
+                v.y = (Real)(-amp0 * sn);
+                st[bswz(z0 + j * NTH, G)] = v;
+            }
+        }
+    }
+    __syncthreads();
+    // bits S-5..S-1 in registers as the phases are formed
+    const uint16_t* Xs = a.eidx + off;
+    for (uint32_t l = t; l < (1u << LB); l += NTH) {
+        const uint32_t bl = opaque(bswz(l, G));
+        V2 v[32];
+        if (intE) {
+            uint16_t x[32];
+#pragma unroll
+            for (int r = 0; r < 32; r++) x[r] = Xs[l | ((uint32_t)r << LB)];
+#pragma unroll
+            for (int r = 0; r < 32; r++) v[r] = lut[x[r]];
+        } else {
+#pragma unroll
+            for (int r = 0; r < 32; r++) v[r] = st[bl ^ bswz((uint32_t)r << LB, G)];
+        }
+        reg_mix<Real, 5>(v, tq);
+#pragma unroll
+        for (int r = 0; r < 32; r++) st[bl ^ bswz((uint32_t)r << LB, G)] = v[r];
+    }
+    __syncthreads();
+    // bits 0..4
+    for (uint32_t q = t; q < (1u << LB); q += NTH) {
+        const uint32_t bq = opaque(bswz(q << 5, G));
+        V2 v[32];
+#pragma unroll
+        for (int r = 0; r < 32; r++) v[r] = st[bq ^ bswz((uint32_t)r, G)];
+        reg_mix<Real, 5>(v, tq);
+#pragma unroll
+        for (int r = 0; r < 32; r++) st[bq ^ bswz((uint32_t)r, G)] = v[r];
+    }
+    __syncthreads();
+    // bits 5..S-6 on the way from LDS to the slab
+    for (uint32_t gq = t; gq < (1u << (S - MB)); gq += NTH) {
+        const uint32_t zb = (gq & 31u) | ((gq >> 5) << (5 + MB));
+        const uint32_t bz = opaque(bswz(zb, G));
+        V2 v[1 << MB];
+#pragma unroll
+        for (int r = 0; r < (1 << MB); r++) v[r] = st[bz ^ bswz((uint32_t)r << 5, G)];
+        reg_mix<Real, MB>(v, tq);
+#pragma unroll
+        for (int r = 0; r < (1 << MB); r++) Ss[zb | ((uint32_t)r << 5)] = v[r];
+    }
+}
+
+template <typename Real, int NTH, int S, int NH>
+__global__ void __launch_bounds__(NTH) k_batch_columns(const BatchArgs a) {
+    using V2 = typename V2T<Real>::type;
+    constexpr int U = kBatchUnroll;
+    constexpr int NV = 1 << NH;  // high-bit values of one column
+    __shared__ double red[NTH / 64][2];
+    const int t = threadIdx.x;
+    const int n = S + NH;
+    const uint32_t s = blockIdx.x >> NH;
+    const uint32_t cb = blockIdx.x & (NV - 1u);
+    const int64_t g = a.s_base + s;
+    const int u = a.s_u0 + (int)(g / a.nb);
+    const int b = (int)(g % a.nb);
+    const BatchInst in = a.inst[a.unit_inst[u]];
+    const bool intE = in.lut_n > 0;
+    const int xmin = intE ? (int)in.emin - in.lut_lo : 0;  // table index of the ground energy
+    uint32_t fl;
+    const Real tq = (Real)tan(batch_reduce_beta(a.betas[b], n, fl));
+    const V2* __restrict__ Sv = reinterpret_cast<const V2*>(a.slab) + ((uint64_t)s << n);
+    const uint16_t* X = a.eidx + in.eoff;
+    const double* E = a.etab + in.eoff;
+    constexpr uint32_t ncol = 1u << (S - NH);  // columns of this workgroup
+    const uint32_t c0 = cb << (S - NH);
+    double r_e = 0.0, r_p = 0.0;
+    for (uint32_t lc = t; lc < ncol; lc += NTH) {
+        const uint32_t l = opaque(c0 + lc);
+        V2 v[NV];
+#pragma unroll
+        for (int r = 0; r < NV; r++) v[r] = Sv[((uint32_t)r << S) | l];
+        reg_mix<Real, NH>(v, tq);
+        if (intE) {
+#pragma unroll
+            for (int r0 = 0; r0 < NV; r0 += U) {
+                constexpr int W = NV < U ? NV : U;
+                uint16_t x[W];
+#pragma unroll
+                for (int j = 0; j < W; j++) x[j] = X[(((uint32_t)(r0 + j) << S) | l) ^ fl];
+#pragma unroll
+                for (int j = 0; j < W; j++) {
+                    const int r = r0 + j;
+                    const double p2 = (double)v[r].x * v[r].x + (double)v[r].y * v[r].y;
+                    r_e += (double)(in.lut_lo + (int)x[j]) * p2;
+                    if ((int)x[j] == xmin) r_p += p2;
+                }
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < NV; r++) {
+                const double p2 = (double)v[r].x * v[r].x + (double)v[r].y * v[r].y;
+                const double e = E[(((uint32_t)r << S) | l) ^ fl];
+                r_e += e * p2;
+                if (fabs(e - in.emin) <= in.etol) r_p += p2;
+            }
+        }
+    }
+    // fixed-order workgroup sum
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        r_e += __shfl_xor(r_e, o);
+        r_p += __shfl_xor(r_p, o);
+    }
+    if ((t & 63) == 0) {
+        red[t >> 6][0] = r_e;
+        red[t >> 6][1] = r_p;
+    }
+    __syncthreads();
+    if (t == 0) {
+        double se = 0.0, sp = 0.0;
+        for (int w = 0; w < NTH / 64; w++) {
+            se += red[w][0];
+            sp += red[w][1];
+        }
+        a.part[2 * (uint64_t)blockIdx.x] = se;
+        a.part[2 * (uint64_t)blockIdx.x + 1] = sp;
+    }
+}
+
+template <typename Real>
+static int launch_batch_columns(const BatchArgs& a, unsigned grid, hipStream_t st) {
+    switch (a.s_n - 13) {
+        case 1: hipLaunchKernelGGL((k_batch_columns<Real, 256, 13, 1>), dim3(grid), dim3(256), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_batch_columns<Real, 256, 13, 2>), dim3(grid), dim3(256), 0, st, a); break;
+        case 3: hipLaunchKernelGGL((k_batch_columns<Real, 256, 13, 3>), dim3(grid), dim3(256), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_batch_columns<Real, 256, 13, 4>), dim3(grid), dim3(256), 0, st, a); break;
+        case 5: hipLaunchKernelGGL((k_batch_columns<Real, 256, 13, 5>), dim3(grid), dim3(256), 0, st, a); break;
+        default: return (int)hipErrorInvalidValue;
+    }
+    return (int)hipGetLastError();
+}
+
+__global__ void __launch_bounds__(256) k_batch_finish(const BatchArgs a, int S) {
+    const int s = blockIdx.x * 256 + threadIdx.x;
+    if (s < a.f_count) batch_finish_state(a, S, a.f_n, a.f_u0, a.f_base, a.f_part, s);
+}
+
+int launch_batch_sliced(int dtype, const BatchArgs& a, int wide, void* stream) {
+    hipStream_t st = (hipStream_t)stream;
+    const int S = batch_lds_bits(dtype, wide);
+    if (S != 13 || a.s_n <= S || a.s_n > S + 5 || a.s_count < 1) return (int)hipErrorInvalidValue;
+    const unsigned grid = (unsigned)a.s_count << (a.s_n - S);
+    const int nth = dtype == 2 ? 512 : 256;
+    const unsigned fin = a.f_count > 0 ? (unsigned)((a.f_count + nth - 1) / nth) : 0u;
+    if (dtype == 2)
+        hipLaunchKernelGGL((k_batch_slices<double, 512, 13, 1024, 1>), dim3(grid + fin), dim3(512), 0, st, a);
+    else
+        hipLaunchKernelGGL((k_batch_slices<float, 256, 13, 1024, 2>), dim3(grid + fin), dim3(256), 0, st, a);
+    int e = (int)hipGetLastError();
+    if (e) return e;
+    return dtype == 2 ? launch_batch_columns<double>(a, grid, st) : launch_batch_columns<float>(a, grid, st);
+}
+
+int launch_batch_finish(const BatchArgs& a, void* stream) {
+    if (a.f_count < 1) return 0;
+    hipLaunchKernelGGL(k_batch_finish, dim3((unsigned)((a.f_count + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
+                       a, 13);
+    return (int)hipGetLastError();
+}
+
 // Variants: complex128 2^13-amplitude LDS states, four waves (wide = 0) or eight (wide = 1);
 // complex64 2^14 states with eight
 // waves (wide = 1) or four (wide = 0), one workgroup per CU; complex64 2^13 states with four

@@ -17,8 +17,9 @@ Targets (--targets, comma list):
             c64g14 (complex64 two-vector kernels).  The forward choices are
             kept while these are tuned.
   batch   : the p = 1 landscape scan over 2048 instances of n in 10..18 on a
-            32 x 32 grid (size key 0).  Knobs: batchwide (complex64) or
-            batch128 (complex128).
+            32 x 32 grid (size key 0).  Knobs: batchslab (MiB of the slab of
+            one sliced launch, 0 = per-workgroup slots) and batchwide
+            (complex64) or batch128 (complex128).
 Search: coordinate descent from the built-in defaults (each knob in turn, the
 others at their current best), two rounds, every candidate timed on the same
 allocation as the median of --reps runs after one untimed run.  Knob values
@@ -44,7 +45,8 @@ FORWARD_C128 = {"cmin128": [3, 4, 5], "c128t14": [0, 1]}
 FORWARD_C64 = {"cmin64": [4, 5, 6], "c64occ": [1, 0], "c64t13": [0, 1]}
 GRAD = {"adjzeta": [-1, 0, 1], "kc34": [1, 0]}
 GRAD_C64 = {"c64g4": [1, 0], "c64g14": [2, 0, 1]}
-BATCH = {"c64": {"batchwide": [2, 1, 0]}, "c128": {"batch128": [1, 0]}}
+BATCH = {"c64": {"batchslab": [256, 128, 192, 384, 0], "batchwide": [2, 1, 0]},
+         "c128": {"batchslab": [256, 128, 192, 384, 0], "batch128": [1, 0]}}
 
 
 def _median(xs):
@@ -122,7 +124,8 @@ def main(argv=None):
 
     torch.cuda.set_device(0)
     sv.tune_load(None)  # tune against the built-in defaults
-    every = {**FORWARD, **FORWARD_C128, **FORWARD_C64, **GRAD, **GRAD_C64, "batchwide": [], "batch128": []}
+    every = {**FORWARD, **FORWARD_C128, **FORWARD_C64, **GRAD, **GRAD_C64, "batchwide": [], "batch128": [],
+             "batchslab": []}
     defaults = {k: sv.tune_get(k) for k in every}
     lines, report = [], {}
     for dtype in args.dtype:

@@ -559,11 +559,16 @@ def test_batch_scan_vs_oracle(sv, orc, dtype):
 
 @pytest.mark.parametrize("dtype,knob,val", [("c64", "batchwide", 0), ("c64", "batchwide", 1),
                                             ("c64", "batchwide", 2), ("c128", "batch128", 0),
-                                            ("c128", "batch128", 1)])
+                                            ("c128", "batch128", 1), ("c64", "batchslab", 0),
+                                            ("c64", "batchslab", 1), ("c128", "batchslab", 0),
+                                            ("c128", "batchslab", 1)])
 def test_batch_scan_variants(sv, orc, dtype, knob, val):
     """Every batch kernel variant (complex64: one workgroup per CU with 2^14 LDS
     states and four or eight waves, or two per CU with 2^13; complex128: four or
-    eight waves) against the oracle."""
+    eight waves) against the oracle.  States above the 2^13-amplitude LDS tile
+    take the sliced path by default; batchslab = 0 sends them through the
+    per-workgroup slots instead, and a 1 MiB slab makes launches of one or two
+    states that split an instance's beta row."""
     ns = [3, 9, 12, 13, 14, 15, 17, 18]
     insts = [I.regular3_pm1(n, 520 + k) if n >= 4 else instance_for(n, "real", 520 + k) for k, n in enumerate(ns)]
     insts.append(I.random_real(14, 25, 78))
