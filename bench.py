@@ -270,17 +270,18 @@ def main():
             # tangent-form mixer (4 flops) and |psi|^2, E |psi|^2 for the sums (6 flops)
             flops = float(np.sum(2.0 ** ns * (4 * ns + 6))) * len(gb) * len(bb)
             peak = 157.3e12 if dt == "c64" else 78.6e12
-            # memory traffic of the scan per grid point: states above the 2^13-amplitude LDS slice
-            # write and read the scratch slot once (2 x amplitude bytes) and read the 16-bit energy
-            # index twice (phase, sums); LDS-resident states only read the index twice
+            # data movement of the scan per grid point: states above the 2^13-amplitude LDS slice
+            # write and read their slab once (2 x amplitude bytes; the 256 MiB slab of a launch
+            # stays in the last-level cache, so this is cache traffic, not HBM traffic) and read
+            # the 16-bit energy index twice (phase, sums); LDS-resident states read the index twice
             es = 8 if dt == "c64" else 16
             big = ns > 13
             mem = float(np.sum(2.0 ** ns[big]) * (2 * es + 4) + np.sum(2.0 ** ns[~big]) * 4) * len(gb) * len(bb)
             extras[f"batch_scan_{dt}"] = {"ms": round(msb, 3), "items": items, "items_per_s": items / (msb * 1e-3),
                                           "amp_updates_per_s": upd / (msb * 1e-3),
                                           "valu_frac": flops / (msb * 1e-3) / peak,
-                                          "mem_model_GBps": round(mem / (msb * 1e-3) / 1e9, 1),
-                                          "mem_frac": round(mem / (msb * 1e-3) / (HBM_PEAK_GBS * 1e9), 4)}
+                                          "slab_and_index_GBps": round(mem / (msb * 1e-3) / 1e9, 1),
+                                          "batchslab_MiB": sv.tune_get("batchslab")}
             log(f"[bench] batch scan {dt}: {msb:.1f} ms for {items} items")
         del Hb
     if "optimizer" in legs:

@@ -1571,7 +1571,9 @@ __device__ void lds_mixer(typename V2T<Real>::type* st, int nb, Real t) {
 // instances read 16-bit table indices (E(z) - lut_lo) and take the phase
 // 2^{-n/2} exp(-i gamma E) from an LDS table; the others read E(z) in FP64 and
 // take sincos.  Table reads are issued kBatchUnroll at a time per thread.
-template <typename Real, int NTH, int S, int LUTN, int MINW = 1>
+// SLOTS = false drops the slot code (registers for the LDS-resident path only):
+// the variant for queues that hold only units with n <= S.
+template <typename Real, int NTH, int S, int LUTN, int MINW = 1, bool SLOTS = true>
 __global__ void __launch_bounds__(NTH, MINW) k_batch_scan(const BatchArgs a) {
     using V2 = typename V2T<Real>::type;
     constexpr int G = BatchCfg<Real>::G;
@@ -1721,7 +1723,7 @@ __global__ void __launch_bounds__(NTH, MINW) k_batch_scan(const BatchArgs a) {
                     }
                     obs_block(0, z0, N, fl, v, r_e, r_p);
                 }
-            } else {
+            } else if constexpr (SLOTS) {
                 // low S bits slice by slice, written to this workgroup's slot: bits
                 // S-5..S-1 in registers as the phases are formed, bits 0..4 in LDS,
                 // bits 5..S-6 on the way from LDS to the slot
@@ -2140,6 +2142,15 @@ int batch_lds_bits(int dtype, int wide) { return dtype == 2 ? 13 : (wide == 2 ? 
 int batch_lut_cap(int, int) { return 1024; }
 
 int launch_batch_scan(int dtype, const BatchArgs& a, int grid, int wide, void* stream) {
+    if (a.scratch_elems == 0 && ((dtype == 2 && wide == 1) || (dtype != 2 && wide == 2))) {  // LDS-resident units only
+        if (dtype == 2)
+            hipLaunchKernelGGL((k_batch_scan<double, 512, 13, 1024, 1, false>), dim3(grid), dim3(512), 0,
+                               (hipStream_t)stream, a);
+        else
+            hipLaunchKernelGGL((k_batch_scan<float, 256, 13, 1024, 2, false>), dim3(grid), dim3(256), 0,
+                               (hipStream_t)stream, a);
+        return (int)hipGetLastError();
+    }
     if (dtype == 2 && wide == 1)
         hipLaunchKernelGGL((k_batch_scan<double, 512, 13, 1024>), dim3(grid), dim3(512), 0, (hipStream_t)stream, a);
     else if (dtype == 2)
