@@ -111,6 +111,18 @@ class OptResult:
         return OptResult(**d)
 
 
+def time_to_energy(result: "OptResult", target: float) -> Optional[dict]:
+    """Simulator seconds and calls until the run first reached <H_C> <= target
+    (None if it never did): the fair comparison of two optimisers that stop at
+    different energies."""
+    t = 0.0
+    for c in result.history:
+        t += c.seconds
+        if c.energy <= target:
+            return {"seconds": t, "calls": c.index + 1}
+    return None
+
+
 class _Budget(Exception):
     pass
 

@@ -169,3 +169,20 @@ def test_device_loop_matches_oracle_loop(orc, dtype):
     e, pg = dev.energy(res.gamma, res.beta)
     assert abs(e - res.energy) <= etol
     dev.close()
+
+
+def test_time_to_energy(orc):
+    """Simulator seconds and calls until the running energy first reaches a
+    target: the first call at or below it, None if no call is."""
+    _, sim = small_problem(orc)
+    g0, b0 = I.linear_ramp_params(2)
+    res = O.optimize_qaoa(sim, g0, b0, method="SLSQP", max_calls=60)
+    es = [c.energy for c in res.history]
+    assert O.time_to_energy(res, min(es) - 1.0) is None
+    hit = O.time_to_energy(res, es[0])
+    assert hit["calls"] == 1 and hit["seconds"] == pytest.approx(res.history[0].seconds)
+    k = int(np.argmin(es))
+    hit = O.time_to_energy(res, min(es))
+    first = next(i for i, e in enumerate(es) if e <= min(es))
+    assert hit["calls"] == first + 1 <= k + 1
+    assert hit["seconds"] == pytest.approx(sum(c.seconds for c in res.history[:first + 1]))
