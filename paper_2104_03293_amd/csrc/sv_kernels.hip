@@ -366,37 +366,39 @@ __device__ __forceinline__ void mix_round(Real (&vr)[NV][1 << R], Real (&vi)[NV]
     }
 }
 
-// A double that every lane reads from the same address, moved to scalar
-// registers (the compiler cannot prove such loads uniform after a barrier).
-__device__ __forceinline__ double uniform_ld(const double* p) {
-    const long long v = *reinterpret_cast<const long long*>(p);
-    const int lo = __builtin_amdgcn_readfirstlane((int)(v & 0xffffffffll));
-    const int hi = __builtin_amdgcn_readfirstlane((int)(v >> 32));
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
-
 // General single-qubit layer, register slots: slot k holds tile bit
 // (rbpack >> 4k) & 15 and applies that bit's matrix M[l] to every register
 // pair (bit k = 0, bit k = 1).  Inactive slots read the identity entry of tile
 // bit 15 (never a qubit of a 13- or 14-bit tile), which keeps the code
 // branch-free.  REALM: every matrix is real (two FMAs per amplitude instead
-// of eight).
+// of eight).  The matrices are read through the constant address space (the
+// host writes them before the launch): scalar loads of every slot's entries,
+// issued together ahead of the butterflies.
 template <typename Real, int R, bool REALM>
 __device__ __forceinline__ void gen_round(Real (&vr)[1][1 << R], Real (&vi)[1][1 << R], int act, uint32_t rbpack,
-                                          const double* __restrict__ M) {
+                                          const SV_CONST double* __restrict__ M) {
     constexpr int NR = 1 << R;
+    Real me[R][8];  // slot k: a0 b0 c0 d0 (real parts), then a1 b1 c1 d1 (imaginary parts)
 #pragma unroll
     for (int k = 0; k < R; k++) {
         const bool on = (act >> k) & 1;
-        const double* m = M + 8 * (on ? ((rbpack >> (4 * k)) & 15u) : 15u);
-        const Real a0 = (Real)uniform_ld(m), b0 = (Real)uniform_ld(m + 2);
-        const Real c0 = (Real)uniform_ld(m + 4), d0 = (Real)uniform_ld(m + 6);
+        const SV_CONST double* m = M + 8 * (on ? ((rbpack >> (4 * k)) & 15u) : 15u);
+#pragma unroll
+        for (int j = 0; j < 4; j++) me[k][j] = (Real)m[2 * j];
+        if constexpr (!REALM) {
+#pragma unroll
+            for (int j = 0; j < 4; j++) me[k][4 + j] = (Real)m[2 * j + 1];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        const Real a0 = me[k][0], b0 = me[k][1], c0 = me[k][2], d0 = me[k][3];
         Real a1 = 0, b1 = 0, c1 = 0, d1 = 0;
         if constexpr (!REALM) {
-            a1 = (Real)uniform_ld(m + 1);
-            b1 = (Real)uniform_ld(m + 3);
-            c1 = (Real)uniform_ld(m + 5);
-            d1 = (Real)uniform_ld(m + 7);
+            a1 = me[k][4];
+            b1 = me[k][5];
+            c1 = me[k][6];
+            d1 = me[k][7];
         }
 #pragma unroll
         for (int r = 0; r < NR; r++) {
@@ -420,16 +422,22 @@ __device__ __forceinline__ void gen_round(Real (&vr)[1][1 << R], Real (&vi)[1][1
 
 // General single-qubit layer, lane bit POS (the partner lane is lane ^ 2^POS):
 // the lane whose bit is 0 holds u and forms m00 u + m01 v, its partner forms
-// m10 u + m11 v.  l is the tile bit of that lane position.
+// m10 u + m11 v.  l is the tile bit of that lane position.  Both rows are read
+// as scalars; each lane selects its own.
 template <int CTRL, int POS, typename Real, int R, bool REALM>
 __device__ __forceinline__ void gen_lane(Real (&vr)[1][1 << R], Real (&vi)[1][1 << R], int l,
-                                         const double* __restrict__ M) {
+                                         const SV_CONST double* __restrict__ M) {
     constexpr int NR = 1 << R;
-    const double* m = M + 8 * l;
+    const SV_CONST double* m = M + 8 * l;
     const bool hi = ((threadIdx.x >> POS) & 1u) != 0;
-    const int o = hi ? 6 : 0, x = hi ? 4 : 2;
-    const Real sr = (Real)m[o], orr = (Real)m[x];
-    const Real si = REALM ? (Real)0 : (Real)m[o + 1], oi = REALM ? (Real)0 : (Real)m[x + 1];
+    const double m0 = m[0], m2 = m[2], m4 = m[4], m6 = m[6];
+    const Real sr = (Real)(hi ? m6 : m0), orr = (Real)(hi ? m4 : m2);
+    Real si = (Real)0, oi = (Real)0;
+    if constexpr (!REALM) {
+        const double m1 = m[1], m3 = m[3], m5 = m[5], m7 = m[7];
+        si = (Real)(hi ? m7 : m1);
+        oi = (Real)(hi ? m5 : m3);
+    }
 #pragma unroll
     for (int r = 0; r < NR; r++) {
         const Real pr = lane_xor<CTRL>(vr[0][r]), pi = lane_xor<CTRL>(vi[0][r]);
@@ -652,7 +660,8 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                     if constexpr (GEN != 0) {
                         // general single-qubit layers (one vector, no pending scale)
                         static_assert(NV == 1, "general layers are one-vector passes");
-                        const double* __restrict__ M = a.gmat + op.qidx * kGenBlock;
+                        const SV_CONST double* __restrict__ M =
+                            (const SV_CONST double*)(a.gmat + op.qidx * kGenBlock);
                         constexpr bool RM = GEN == 2;
                         gen_round<Real, R, RM>(vr, vi, act, L->rbpack, M);
                         const int dl = L->dpp;
