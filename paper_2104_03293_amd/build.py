@@ -20,6 +20,9 @@ ROOT = HERE.parent
 ARCH = os.environ.get("SV_OFFLOAD_ARCH", "gfx950")
 LIB = HERE / "libsv.so"
 LIB_SAN = HERE / "libsv_san.so"
+# host code of the C ABI, and the entry point that allocates nothing
+HOST_SRCS = [CSRC / "sv_host_core.cpp", CSRC / "sv_plan.cpp", CSRC / "sv_api.cpp", CSRC / "sv_batch.cpp",
+             CSRC / "sv_noalloc.hip"]
 CLANG_DIR = Path(os.environ.get("SV_CLANG_DIR", "/opt/rocm/llvm/bin"))
 
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
@@ -49,7 +52,7 @@ def _compile(src: Path, obj: Path, verbose: bool, extra=()) -> None:
 def build(verbose: bool = False) -> Path:
     objdir = HERE / "_build"
     objdir.mkdir(exist_ok=True)
-    srcs = [CSRC / "sv_kernels.hip", CSRC / "sv_api.cpp", CSRC / "sv_noalloc.hip"]
+    srcs = [CSRC / "sv_kernels.hip", *HOST_SRCS]
     objs = [objdir / (s.stem + ".o") for s in srcs]
     with ThreadPoolExecutor(max_workers=len(srcs)) as ex:
         list(ex.map(lambda so: _compile(so[0], so[1], verbose), zip(srcs, objs)))
@@ -78,7 +81,7 @@ def build_sanitized(verbose: bool = False, out: Path | None = None) -> Path:
     kobj = objdir / "sv_kernels.o"
     if not kobj.exists():
         _compile(CSRC / "sv_kernels.hip", kobj, verbose)
-    srcs = [CSRC / "sv_api.cpp", CSRC / "sv_noalloc.hip"]
+    srcs = list(HOST_SRCS)
     objs = [objdir / (s.stem + "_san.o") for s in srcs]
     with ThreadPoolExecutor(max_workers=len(srcs)) as ex:
         list(ex.map(lambda so: _compile(so[0], so[1], verbose, HOST_SAN_FLAGS), zip(srcs, objs)))

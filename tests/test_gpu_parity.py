@@ -773,3 +773,19 @@ def test_autograd_function_forward_only(sv, orc, dtype):
     assert np.array_equal(lam.to_numpy(), marker.astype(lam.to_numpy().dtype))
     f = orc.energy_of(inst, g0, b0)
     assert abs(ref - f) <= energy_tol(orc, inst, f)
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_mixer_tables_rebuilt_after_last_state_freed(sv, orc, dtype):
+    """Mixer-only programs use instance-free geometry tables that the library
+    frees with its last state; a state made afterwards rebuilds them."""
+    import gc
+
+    gc.collect()
+    for n in (15, 21, 15):
+        psi0 = rand_state(n, 700 + n)
+        s = sv.State(n, dtype)
+        s.from_numpy(psi0)
+        sv.mixer(s, 0.61)
+        assert np.max(np.abs(s.to_numpy() - orc.mixer(n, psi0, 0.61))) <= AMP_TOL[dtype]
+        s.close()
+        gc.collect()
