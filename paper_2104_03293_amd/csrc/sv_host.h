@@ -146,6 +146,13 @@ struct Program {
     int nq = 0;                      // qubits per layer
 };
 
+// Matrices of general single-qubit layers as the kernels apply them.
+struct GenLayers {
+    std::vector<double> m;       // [layer][qubit][8]
+    std::vector<uint8_t> unit;   // per layer: unit-diagonal form (MIX_GUNIT)
+    std::vector<double> mod;     // [layer][qubit]: diagonal modulus of a unit layer, else 1
+};
+
 // Tile shapes of a program: [1] one-vector, [2] two-vector.
 struct Plan {
     std::vector<Geometry> by_nv[3];  // [1]: one-vector tile shape, [2]: two-vector shape

@@ -59,6 +59,7 @@ std::map<std::string, int> g_knobs = {
     {"c64g14", 2},    // complex64 adjoint programs on 14-bit tiles: 1 always, 2 when fewer groups, 0 never
     {"batchslab", 256},  // batch scan, states above the LDS tile: MiB of the cache-resident slab of one
                          // sliced launch (0: per-workgroup slots in device memory)
+    {"genunit", 1},   // general single-qubit layers: 1 = unit-diagonal form where the matrices allow it
     {"ntinit", 1},    // write-only first passes: 1 = nontemporal stores
     {"split", 0},     // bits above the contiguous tile: 0 = near-equal groups, 1 = largest groups first
     {"xcd", -1},      // x > 0: XCD-aware tile order, 8 * 2^(x-1) interleaved streams of contiguous tiles;
@@ -77,7 +78,7 @@ const std::map<std::string, std::pair<int, int>> g_knob_range = {
     {"fuse", {0, 1}},    {"cmin64", {0, 8}},   {"cmin128", {0, 8}},  {"ntmin", {0, 64}},   {"persist", {0, 8}},
     {"stagger", {0, 64}}, {"snake", {0, 2}},   {"dpp", {0, 1}},      {"ldsswz", {3, 5}},   {"batchwide", {0, 2}},
     {"batch128", {0, 1}}, {"c64t13", {0, 1}},  {"c64occ", {0, 1}},   {"c64g4", {0, 1}},    {"kc34", {0, 1}},
-    {"c64g14", {0, 2}},  {"ntinit", {0, 1}},   {"batchslab", {0, 4096}},   {"split", {0, 1}},    {"xcd", {-1, 5}},      {"c128t14", {0, 1}}, {"adjzeta", {-1, 1}},
+    {"c64g14", {0, 2}},  {"ntinit", {0, 1}},   {"batchslab", {0, 4096}}, {"genunit", {0, 1}},   {"split", {0, 1}},    {"xcd", {-1, 5}},      {"c128t14", {0, 1}}, {"adjzeta", {-1, 1}},
     {"fail_next_launch", {0, 1}},
 };
 }  // namespace

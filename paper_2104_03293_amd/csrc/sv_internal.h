@@ -44,13 +44,16 @@ enum OpKind : int32_t { OP_MIX = 1, OP_POINT = 2 };
 // a = tan(beta') for |beta'| <= pi/4, and multiplies the vector's uniform
 // pending scale by b = +-cos(beta') per qubit (the host reduces beta modulo pi
 // and splits larger angles into two halves).
-enum MixFlags : int32_t { MIX_PSI = 1, MIX_LAM = 2, MIX_GBETA = 4, MIX_GEN = 8 };
+enum MixFlags : int32_t { MIX_PSI = 1, MIX_LAM = 2, MIX_GBETA = 4, MIX_GEN = 8, MIX_GUNIT = 16 };
 
 // MIX_GEN (one-vector passes): a general single-qubit layer instead.  Every
 // active tile bit l gets its own complex 2x2 matrix m, (u, v) <- (m00 u + m01 v,
 // m10 u + m11 v), read from PassArgs::gmat + qidx * kGenBlock + 8 l as
 // (m00 re, im, m01 re, im, m10 re, im, m11 re, im); u is the amplitude whose
-// bit is 0.
+// bit is 0.  MIX_GUNIT: every matrix of the op has m00 = m11 = 1 (the host's
+// unit-diagonal form), so (u, v) <- (u + m01 v, m10 u + v) at half the
+// arithmetic, and the pending scale is multiplied by Op::b; a pass holds
+// either only such ops or none (PassArgs::gen_unit selects the kernel).
 constexpr int kGenBlock = 16 * 8;
 
 // POINT flags, executed in this order.
@@ -173,6 +176,7 @@ struct PassArgs {
     double* spin_part;      // [ntiles][kTF] spin partials (passes with PT_SPINZ)
     const double* gmat;     // general single-qubit layers (passes whose MIX ops carry MIX_GEN), else null
     int32_t gen_real;       // every general layer of the pass is real
+    int32_t gen_unit;       // every general layer of the pass is in the unit-diagonal form (MIX_GUNIT)
     int32_t kc34;           // two-vector passes with three or four layouts: straight-line kernels
     int32_t qf;             // one-vector pass of the adjoint sweeps: 1 quadratic forms, 2 also PT_ZETA / PT_EFORM,
                             // 3 also PT_REDUCE before PT_ZETA

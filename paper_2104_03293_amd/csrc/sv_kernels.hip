@@ -371,13 +371,55 @@ __device__ __forceinline__ void mix_round(Real (&vr)[NV][1 << R], Real (&vi)[NV]
 // pair (bit k = 0, bit k = 1).  Inactive slots read the identity entry of tile
 // bit 15 (never a qubit of a 13- or 14-bit tile), which keeps the code
 // branch-free.  REALM: every matrix is real (two FMAs per amplitude instead
-// of eight).  The matrices are read through the constant address space (the
-// host writes them before the launch): scalar loads of every slot's entries,
-// issued together ahead of the butterflies.
-template <typename Real, int R, bool REALM>
+// of eight).  unit: every matrix has a unit diagonal (one FMA per amplitude
+// for real matrices, four for complex ones).  The matrices are read through
+// the constant address space (the host writes them before the launch): scalar
+// loads of every slot's entries, issued together ahead of the butterflies.
+template <typename Real, int R, bool REALM, bool UNIT>
 __device__ __forceinline__ void gen_round(Real (&vr)[1][1 << R], Real (&vi)[1][1 << R], int act, uint32_t rbpack,
                                           const SV_CONST double* __restrict__ M) {
     constexpr int NR = 1 << R;
+    if constexpr (UNIT) {
+        // off-diagonal entries only: (u, v) <- (u + m01 v, m10 u + v)
+        Real mo[R][4];  // slot k: m01 re, m10 re, m01 im, m10 im
+#pragma unroll
+        for (int k = 0; k < R; k++) {
+            const bool on = (act >> k) & 1;
+            const SV_CONST double* m = M + 8 * (on ? ((rbpack >> (4 * k)) & 15u) : 15u);
+            mo[k][0] = (Real)m[2];
+            mo[k][1] = (Real)m[4];
+            if constexpr (!REALM) {
+                mo[k][2] = (Real)m[3];
+                mo[k][3] = (Real)m[5];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < R; k++) {
+            const Real b0 = mo[k][0], c0 = mo[k][1];
+            Real b1 = 0, c1 = 0;
+            if constexpr (!REALM) {
+                b1 = mo[k][2];
+                c1 = mo[k][3];
+            }
+#pragma unroll
+            for (int r = 0; r < NR; r++) {
+                if (r & (1 << k)) continue;
+                const int r2 = r | (1 << k);
+                const Real ur = vr[0][r], ui = vi[0][r], wr = vr[0][r2], wi = vi[0][r2];
+                if constexpr (REALM) {
+                    vr[0][r] = fma(b0, wr, ur);
+                    vi[0][r] = fma(b0, wi, ui);
+                    vr[0][r2] = fma(c0, ur, wr);
+                    vi[0][r2] = fma(c0, ui, wi);
+                } else {
+                    vr[0][r] = fma(b0, wr, fma(-b1, wi, ur));
+                    vi[0][r] = fma(b0, wi, fma(b1, wr, ui));
+                    vr[0][r2] = fma(c0, ur, fma(-c1, ui, wr));
+                    vi[0][r2] = fma(c0, ui, fma(c1, ur, wi));
+                }
+            }
+        }
+    } else {
     Real me[R][8];  // slot k: a0 b0 c0 d0 (real parts), then a1 b1 c1 d1 (imaginary parts)
 #pragma unroll
     for (int k = 0; k < R; k++) {
@@ -418,18 +460,42 @@ __device__ __forceinline__ void gen_round(Real (&vr)[1][1 << R], Real (&vi)[1][1
             }
         }
     }
+    }
 }
 
 // General single-qubit layer, lane bit POS (the partner lane is lane ^ 2^POS):
 // the lane whose bit is 0 holds u and forms m00 u + m01 v, its partner forms
 // m10 u + m11 v.  l is the tile bit of that lane position.  Both rows are read
-// as scalars; each lane selects its own.
-template <int CTRL, int POS, typename Real, int R, bool REALM>
+// as scalars; each lane selects its own.  unit: unit diagonal, each lane adds
+// its off-diagonal entry times the partner's value to its own.
+template <int CTRL, int POS, typename Real, int R, bool REALM, bool UNIT>
 __device__ __forceinline__ void gen_lane(Real (&vr)[1][1 << R], Real (&vi)[1][1 << R], int l,
                                          const SV_CONST double* __restrict__ M) {
     constexpr int NR = 1 << R;
     const SV_CONST double* m = M + 8 * l;
     const bool hi = ((threadIdx.x >> POS) & 1u) != 0;
+    if constexpr (UNIT) {
+        const double m2 = m[2], m4 = m[4];
+        const Real orr = (Real)(hi ? m4 : m2);
+        Real oi = (Real)0;
+        if constexpr (!REALM) {
+            const double m3 = m[3], m5 = m[5];
+            oi = (Real)(hi ? m5 : m3);
+        }
+#pragma unroll
+        for (int r = 0; r < NR; r++) {
+            const Real pr = lane_xor<CTRL>(vr[0][r]), pi = lane_xor<CTRL>(vi[0][r]);
+            const Real xr = vr[0][r], xi = vi[0][r];
+            if constexpr (REALM) {
+                vr[0][r] = fma(orr, pr, xr);
+                vi[0][r] = fma(orr, pi, xi);
+            } else {
+                vr[0][r] = fma(orr, pr, fma(-oi, pi, xr));
+                vi[0][r] = fma(orr, pi, fma(oi, pr, xi));
+            }
+        }
+        return;
+    }
     const double m0 = m[0], m2 = m[2], m4 = m[4], m6 = m[6];
     const Real sr = (Real)(hi ? m6 : m0), orr = (Real)(hi ? m4 : m2);
     Real si = (Real)0, oi = (Real)0;
@@ -662,12 +728,14 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                         static_assert(NV == 1, "general layers are one-vector passes");
                         const SV_CONST double* __restrict__ M =
                             (const SV_CONST double*)(a.gmat + op.qidx * kGenBlock);
-                        constexpr bool RM = GEN == 2;
-                        gen_round<Real, R, RM>(vr, vi, act, L->rbpack, M);
+                        // GEN: 1 complex, 2 real, 3 complex unit-diagonal, 4 real unit-diagonal
+                        constexpr bool RM = GEN == 2 || GEN == 4;
+                        constexpr bool UN = GEN >= 3;
+                        gen_round<Real, R, RM, UN>(vr, vi, act, L->rbpack, M);
                         const int dl = L->dpp;
-                        if (dl & 8) gen_lane<kLaneX8, 3, Real, R, RM>(vr, vi, tmask_bit(L->tmask, 3), M);
+                        if (dl & 8) gen_lane<kLaneX8, 3, Real, R, RM, UN>(vr, vi, tmask_bit(L->tmask, 3), M);
                         if constexpr (sizeof(Real) == 4 && T == 14) {
-                            if (dl & 16) gen_lane<kLaneX16, 4, Real, R, RM>(vr, vi, tmask_bit(L->tmask, 4), M);
+                            if (dl & 16) gen_lane<kLaneX16, 4, Real, R, RM, UN>(vr, vi, tmask_bit(L->tmask, 4), M);
                         }
                         return;
                     }
@@ -701,6 +769,7 @@ __global__ void __launch_bounds__(1 << (T - R), MINB) k_pass(const PassArgs a) {
                     for (int step = 0; step < K; step++) round(step);
                 }
                 if (op.flags & MIX_GBETA) wave_add<NS>(s_red, op.slot, gsum);
+                if constexpr (GEN >= 3) pend[0] *= op.b;  // unit-diagonal layers: product of the diagonal moduli
             } else {  // OP_POINT
                 // Walk the registers in Gray-code order: consecutive registers differ in
                 // one bit k, so E changes by +-2 f[k] and the phase by exp(-+2i gamma f[k]).
@@ -1162,31 +1231,37 @@ Shape shape_for(int dtype, int nv, bool grad) {
 }
 
 // Full-tile general-layer passes: layout count, real or complex matrices, nontemporal hints.
-template <typename Real, int T, int R, int NS, int GMB, int NTM>
+template <typename Real, int T, int R, int NS, int GMB, int NTM, int GC = 1, int GR = 2>
 static void launch_gen_fast(const PassArgs& a, dim3 grid, dim3 block, hipStream_t st) {
+    if constexpr (GC == 1) {
+        if (a.gen_unit) {  // unit-diagonal layers: the GEN = 3 / 4 kernels
+            launch_gen_fast<Real, T, R, NS, GMB, NTM, 3, 4>(a, grid, block, st);
+            return;
+        }
+    }
     const bool rm = a.gen_real != 0;
     // three or more layouts with complex matrices on complex128 amplitudes need the whole
     // register file (one workgroup per CU)
-    constexpr int MB = sizeof(Real) == 8 ? 1 : GMB;
+    constexpr int MB = (sizeof(Real) == 8 && GC == 1) ? 1 : GMB;
     if (a.nlayouts == 1) {
-        if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 1, NTM, false, false, 2>), grid, block,
+        if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 1, NTM, false, false, GR>), grid, block,
                                    0, st, a);
-        else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 1, NTM, false, false, 1>), grid, block, 0,
+        else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 1, NTM, false, false, GC>), grid, block, 0,
                                 st, a);
     } else if (a.nlayouts == 2) {
-        if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 2, NTM, false, false, 2>), grid, block,
+        if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 2, NTM, false, false, GR>), grid, block,
                                    0, st, a);
-        else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 2, NTM, false, false, 1>), grid, block, 0,
+        else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 2, NTM, false, false, GC>), grid, block, 0,
                                 st, a);
     } else if (a.kc34 && a.nlayouts == 3) {  // straight-line walk
-        if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 3, NTM, false, false, 2>), grid, block,
+        if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 3, NTM, false, false, GR>), grid, block,
                                    0, st, a);
-        else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MB, false, true, 3, NTM, false, false, 1>), grid, block, 0,
+        else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MB, false, true, 3, NTM, false, false, GC>), grid, block, 0,
                                 st, a);
     } else {
-        if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 0, NTM, false, false, 2>), grid, block,
+        if (rm) hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, GMB, false, true, 0, NTM, false, false, GR>), grid, block,
                                    0, st, a);
-        else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MB, false, true, 0, NTM, false, false, 1>), grid, block, 0,
+        else hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, MB, false, true, 0, NTM, false, false, GC>), grid, block, 0,
                                 st, a);
     }
 }
@@ -1252,6 +1327,9 @@ static int run_pass(const PassArgs& a, void* stream) {
                     launch_gen_fast<Real, T, R, NS, GMB, 3>(a, grid, block, st);
                 else
                     launch_gen_fast<Real, T, R, NS, GMB, 0>(a, grid, block, st);
+            } else if (a.gen_unit) {
+                hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, 1, true, false, 0, 0, false, true, 3>), grid, block,
+                                   0, st, a);
             } else {
                 hipLaunchKernelGGL((k_pass<Real, T, R, 1, NS, 1, true, false, 0, 0, false, true, 1>), grid, block,
                                    0, st, a);

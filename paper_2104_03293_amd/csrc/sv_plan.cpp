@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <array>
+#include <complex>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -245,6 +246,79 @@ static int global_bit(const Geometry& geo, int l) {
     if (l >= geo.n) return -1;
     if (l < geo.c) return l;
     return geo.lo + (l - geo.c);
+}
+
+// General single-qubit layers in unit-diagonal form (kernel side: MIX_GUNIT).
+// A layer whose every matrix M = [[a, b], [c, d]] has |a|, |d| >= 1/4 and
+// |d| = |a| (to 1e-9, as for every unitary) is written M = |a| D N with
+// D = diag(a, d) / |a| and N = [[1, b/a], [c/d, 1]]: the kernel applies N at
+// half the arithmetic of a general 2x2 matrix and multiplies the pass's
+// pending scale by |a|.  D is carried to the right of the later layers of its
+// qubit (N' D = D (D^-1 N' D), and D^-1 N' D again has a unit diagonal) and
+// of the diagonal phase ops (which commute with it), until the next layer in
+// the general form applies M D; the last layer always takes the general form,
+// so the state leaves the program exact.  Observables of |psi|^2 (energy,
+// P_gs, spins) do not see D, whose entries have modulus one.  Layers are
+// applied in index order, each once per qubit (both callers build them so).
+// pass_layers: the layers of each pass; a pass runs one kernel, so its layers
+// all take the same form.
+static GenLayers unit_diagonal_layers(const double* L, int nl, int n, bool enable,
+                                      const std::vector<std::vector<int>>& pass_layers) {
+    using cd = std::complex<double>;
+    GenLayers gl;
+    gl.m.assign(L, L + (size_t)nl * n * 8);
+    gl.unit.assign(nl, 0);
+    gl.mod.assign((size_t)nl * n, 1.0);
+    if (!enable) return gl;
+    for (int ly = 0; ly + 1 < nl; ly++) {
+        const double* M = L + (size_t)ly * n * 8;
+        bool unit = true;
+        for (int q = 0; q < n && unit; q++) {
+            const double* m = M + 8 * q;
+            const double aa = std::abs(cd(m[0], m[1])), ad = std::abs(cd(m[6], m[7]));
+            unit = aa >= 0.25 && ad >= 0.25 && std::abs(ad / aa - 1.0) <= 1e-9;
+        }
+        gl.unit[ly] = unit;
+    }
+    for (bool changed = true; changed;) {  // a pass with a general layer runs every layer in the general form
+        changed = false;
+        for (const std::vector<int>& pl : pass_layers) {
+            bool all = true;
+            for (int ly : pl) all = all && gl.unit[ly];
+            if (all) continue;
+            for (int ly : pl) {
+                changed = changed || gl.unit[ly];
+                gl.unit[ly] = 0;
+            }
+        }
+    }
+    std::vector<cd> d0(n, cd(1.0)), d1(n, cd(1.0));  // pending diagonal of each qubit
+    for (int ly = 0; ly < nl; ly++) {
+        const double* M = L + (size_t)ly * n * 8;
+        const bool unit = gl.unit[ly] != 0;
+        for (int q = 0; q < n; q++) {
+            const double* m = M + 8 * q;
+            const cd a(m[0], m[1]), b(m[2], m[3]), c(m[4], m[5]), d(m[6], m[7]);
+            double* o = gl.m.data() + ((size_t)ly * n + q) * 8;
+            if (unit) {
+                // D^-1 N D with D = diag(d0, d1): off-diagonals times d1/d0 and d0/d1
+                const double aa = std::abs(a);
+                const cd x = b / a * (d1[q] / d0[q]), y = c / d * (d0[q] / d1[q]);
+                const double v[8] = {1.0, 0.0, x.real(), x.imag(), y.real(), y.imag(), 1.0, 0.0};
+                memcpy(o, v, sizeof(v));
+                gl.mod[(size_t)ly * n + q] = aa;
+                d0[q] *= a / aa;
+                d1[q] *= d / aa;
+            } else {
+                // M D applies the pending diagonal
+                const cd p = a * d0[q], r = b * d1[q], t = c * d0[q], w = d * d1[q];
+                const double v[8] = {p.real(), p.imag(), r.real(), r.imag(), t.real(), t.imag(), w.real(), w.imag()};
+                memcpy(o, v, sizeof(v));
+                d0[q] = d1[q] = cd(1.0);
+            }
+        }
+    }
+    return gl;
 }
 
 // Build the device table for a geometry and (optionally) an instance.
@@ -811,7 +885,8 @@ int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& prog, co
         }
     }
     // general single-qubit layers: one block of kGenBlock doubles per MIX op
-    // (matrix of tile bit l at 8 l; identity for phantom bits)
+    // (matrix of tile bit l at 8 l; identity for phantom bits), in the unit-diagonal
+    // form where the layer allows it
     std::vector<std::array<int, kMaxOps>> genblk(prog.passes.size());
     std::vector<std::array<bool, kMaxOps>> genreal(prog.passes.size());  // every matrix of the op is real
     size_t nblk = 0;
@@ -825,6 +900,19 @@ int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& prog, co
     if (nblk > 0) {
         if (fx) return fail(SV_ERR_UNSUPPORTED, "general layers need allocated scratch");
         if (!prog.layers || prog.nq != s->n) return fail(SV_ERR_ARG, "internal: general layers without matrices");
+        int nl = 0;
+        std::vector<std::vector<int>> pass_layers;
+        for (const Pass& ps : prog.passes) {
+            std::vector<int> pl;
+            for (const Op& op : ps.ops)
+                if (op.kind == OP_MIX && (op.flags & MIX_GEN)) {
+                    nl = std::max(nl, op.qidx + 1);
+                    pl.push_back(op.qidx);
+                }
+            if (!pl.empty()) pass_layers.push_back(pl);
+        }
+        const GenLayers gl = unit_diagonal_layers(prog.layers, nl, s->n, knob_for("genunit", (int)s->dt, s->n) != 0,
+                                                  pass_layers);
         const size_t need = nblk * (size_t)kGenBlock;
         // the staging buffer may still feed the previous call's copy
         HIPCHECK(hipStreamSynchronize(s->stream));
@@ -843,7 +931,8 @@ int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& prog, co
             for (int i = 0; i < kMaxOps; i++) {
                 if (genblk[pi][i] < 0) continue;
                 double* blk = s->w.h_gmat + (size_t)genblk[pi][i] * kGenBlock;
-                const int layer = prog.passes[pi].ops[i].qidx;
+                Op& op = prog.passes[pi].ops[i];
+                const int layer = op.qidx;
                 bool real = true;
                 for (int l = 0; l < kGenBlock / 8; l++) {
                     const int q = l < geo.T ? global_bit(geo, l) : -1;
@@ -851,11 +940,22 @@ int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& prog, co
                         const double id[8] = {1, 0, 0, 0, 0, 0, 1, 0};
                         memcpy(blk + 8 * l, id, sizeof(id));
                     } else {
-                        memcpy(blk + 8 * l, prog.layers + ((size_t)layer * s->n + q) * 8, 8 * sizeof(double));
+                        memcpy(blk + 8 * l, gl.m.data() + ((size_t)layer * s->n + q) * 8, 8 * sizeof(double));
                     }
                     for (int c = 1; c < 8; c += 2) real = real && blk[8 * l + c] == 0.0;
                 }
                 genreal[pi][i] = real;
+                if (gl.unit[layer]) {
+                    // the moduli of the op's qubits (its active tile bits) join the pending scale
+                    double sc = 1.0;
+                    const int l0 = geo.g == 0 ? 0 : geo.c;
+                    for (int l = l0; l < std::min(geo.T, geo.n); l++) {
+                        const int q = global_bit(geo, l);
+                        if (q >= 0) sc *= gl.mod[(size_t)layer * s->n + q];
+                    }
+                    op.flags |= MIX_GUNIT;
+                    op.b = sc;
+                }
             }
         }
         hipError_t e = hipMemcpyAsync(s->w.d_gmat, s->w.h_gmat, need * sizeof(double), hipMemcpyHostToDevice,
@@ -944,8 +1044,12 @@ int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& prog, co
                 if (m & 16u) a.occ4 = 0;
         }
         a.gen_real = 1;
-        for (int i = 0; i < kMaxOps; i++)
-            if (genblk[pi][i] >= 0 && !genreal[pi][i]) a.gen_real = 0;
+        a.gen_unit = 0;
+        for (int i = 0; i < kMaxOps; i++) {
+            if (genblk[pi][i] < 0) continue;
+            if (!genreal[pi][i]) a.gen_real = 0;
+            if (p.ops[i].flags & MIX_GUNIT) a.gen_unit = 1;  // every general op of the pass, by construction
+        }
         hipEvent_t ev0;
         const bool prof = !fx && prof_begin(s->stream, &ev0);
         int e = take_injected_failure() ? (int)hipErrorLaunchFailure : launch_pass((int)s->dt, p.nv, geo.T, a, s->stream);

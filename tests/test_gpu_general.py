@@ -76,6 +76,61 @@ def test_gate_layers_vs_oracle(sv, orc, dtype, n, nl):
     assert np.max(np.abs(s.to_numpy() - ref)) <= AMP_TOL[dtype]
 
 
+def near_identity_unitaries(shape, seed, theta_max=1.2):
+    """Unitaries e^{ig} [[cos t e^{ia}, -sin t e^{-ib}], [sin t e^{ib}, cos t e^{-ia}]]
+    with t <= theta_max, so that |m00| = |m11| >= cos(theta_max)."""
+    rng = np.random.default_rng(seed)
+    t = rng.uniform(0.0, theta_max, size=shape)
+    a, b, g = (rng.uniform(-np.pi, np.pi, size=shape) for _ in range(3))
+    U = np.empty(shape + (2, 2), dtype=np.complex128)
+    U[..., 0, 0] = np.cos(t) * np.exp(1j * a)
+    U[..., 0, 1] = -np.sin(t) * np.exp(-1j * b)
+    U[..., 1, 0] = np.sin(t) * np.exp(1j * b)
+    U[..., 1, 1] = np.cos(t) * np.exp(-1j * a)
+    return U * np.exp(1j * g)[..., None, None]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n", [5, 14, 20])
+def test_gate_layers_unit_diagonal_form(sv, orc, dtype, n):
+    """Layers whose matrices all have |m00| = |m11| >= 1/4 run in the
+    unit-diagonal form (knob genunit): the diagonal phases are carried to the
+    next layer in the general form, here a layer with a Pauli-X and a
+    Hadamard (|m00| below 1/4), and to the last layer.  Real layers (Hadamard,
+    reflections) take the real kernels.  Both forms match the oracle."""
+    nl = 7
+    U = near_identity_unitaries((nl, n), 330 + n)
+    U[3, 0] = [[0, 1], [1, 0]]
+    U[3, n - 1] = HAD
+    U[5] = np.array([[0.6, 0.8], [0.8, -0.6]])  # a real layer (reflections) between complex ones
+    psi0 = rand_state(n, 340 + n)
+    ref = orc.gate_layers(n, psi0, U)
+    out = {}
+    for unit in (1, 0):
+        old = sv.tune_get("genunit")
+        sv.tune_set("genunit", unit)
+        try:
+            s = sv.State(n, dtype)
+            s.from_numpy(psi0)
+            sv.gate_layers(s, U)
+            out[unit] = s.to_numpy()
+        finally:
+            sv.tune_set("genunit", old)
+        assert np.max(np.abs(out[unit] - ref)) <= AMP_TOL[dtype], unit
+    HR = np.broadcast_to(HAD, (9, n, 2, 2))
+    ref = orc.gate_layers(n, psi0, HR)
+    for unit in (1, 0):
+        old = sv.tune_get("genunit")
+        sv.tune_set("genunit", unit)
+        try:
+            s = sv.State(n, dtype)
+            s.from_numpy(psi0)
+            sv.gate_layers(s, HR)
+            assert np.max(np.abs(s.to_numpy() - ref)) <= AMP_TOL[dtype], unit
+        finally:
+            sv.tune_set("genunit", old)
+
+
 def test_gate_layers_non_unitary(sv, orc):
     n = 15
     rng = np.random.default_rng(320)
