@@ -149,7 +149,7 @@ struct Program {
 // Matrices of general single-qubit layers as the kernels apply them.
 struct GenLayers {
     std::vector<double> m;       // [layer][qubit][8]
-    std::vector<uint8_t> unit;   // per layer: unit-diagonal form (MIX_GUNIT)
+    std::vector<uint8_t> unit;   // [layer][qubit]: unit-diagonal form (MIX_GUNIT)
     std::vector<double> mod;     // [layer][qubit]: diagonal modulus of a unit layer, else 1
 };
 

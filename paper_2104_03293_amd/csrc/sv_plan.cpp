@@ -249,8 +249,8 @@ static int global_bit(const Geometry& geo, int l) {
 }
 
 // General single-qubit layers in unit-diagonal form (kernel side: MIX_GUNIT).
-// A layer whose every matrix M = [[a, b], [c, d]] has |a|, |d| >= 1/4 and
-// |d| = |a| (to 1e-9, as for every unitary) is written M = |a| D N with
+// A matrix M = [[a, b], [c, d]] with |a|, |d| >= 1/4 and |d| = |a| (to 1e-9, as
+// for every unitary) is written M = |a| D N with
 // D = diag(a, d) / |a| and N = [[1, b/a], [c/d, 1]]: the kernel applies N at
 // half the arithmetic of a general 2x2 matrix and multiplies the pass's
 // pending scale by |a|.  D is carried to the right of the later layers of its
@@ -260,43 +260,37 @@ static int global_bit(const Geometry& geo, int l) {
 // so the state leaves the program exact.  Observables of |psi|^2 (energy,
 // P_gs, spins) do not see D, whose entries have modulus one.  Layers are
 // applied in index order, each once per qubit (both callers build them so).
-// pass_layers: the layers of each pass; a pass runs one kernel, so its layers
-// all take the same form.
+// pass_ops: the general ops of each pass as (layer, qubits of its tile group).
+// A pass runs one kernel, so its ops all take the same form: the unit form
+// where every matrix of every op of the pass allows it.  An op (a layer on one
+// tile group) occurs in one pass only, so the choice is settled pass by pass.
 static GenLayers unit_diagonal_layers(const double* L, int nl, int n, bool enable,
-                                      const std::vector<std::vector<int>>& pass_layers) {
+                                      const std::vector<std::vector<std::pair<int, std::vector<int>>>>& pass_ops) {
     using cd = std::complex<double>;
     GenLayers gl;
     gl.m.assign(L, L + (size_t)nl * n * 8);
-    gl.unit.assign(nl, 0);
+    gl.unit.assign((size_t)nl * n, 0);
     gl.mod.assign((size_t)nl * n, 1.0);
     if (!enable) return gl;
-    for (int ly = 0; ly + 1 < nl; ly++) {
-        const double* M = L + (size_t)ly * n * 8;
-        bool unit = true;
-        for (int q = 0; q < n && unit; q++) {
-            const double* m = M + 8 * q;
-            const double aa = std::abs(cd(m[0], m[1])), ad = std::abs(cd(m[6], m[7]));
-            unit = aa >= 0.25 && ad >= 0.25 && std::abs(ad / aa - 1.0) <= 1e-9;
-        }
-        gl.unit[ly] = unit;
-    }
-    for (bool changed = true; changed;) {  // a pass with a general layer runs every layer in the general form
-        changed = false;
-        for (const std::vector<int>& pl : pass_layers) {
-            bool all = true;
-            for (int ly : pl) all = all && gl.unit[ly];
-            if (all) continue;
-            for (int ly : pl) {
-                changed = changed || gl.unit[ly];
-                gl.unit[ly] = 0;
-            }
-        }
+    auto eligible = [&](int ly, int q) {
+        if (ly + 1 >= nl) return false;  // the last layer applies what is still pending
+        const double* m = L + ((size_t)ly * n + q) * 8;
+        const double aa = std::abs(cd(m[0], m[1])), ad = std::abs(cd(m[6], m[7]));
+        return aa >= 0.25 && ad >= 0.25 && std::abs(ad / aa - 1.0) <= 1e-9;
+    };
+    for (const auto& ops : pass_ops) {
+        bool all = true;
+        for (const auto& op : ops)
+            for (int q : op.second) all = all && eligible(op.first, q);
+        if (!all) continue;
+        for (const auto& op : ops)
+            for (int q : op.second) gl.unit[(size_t)op.first * n + q] = 1;
     }
     std::vector<cd> d0(n, cd(1.0)), d1(n, cd(1.0));  // pending diagonal of each qubit
     for (int ly = 0; ly < nl; ly++) {
         const double* M = L + (size_t)ly * n * 8;
-        const bool unit = gl.unit[ly] != 0;
         for (int q = 0; q < n; q++) {
+            const bool unit = gl.unit[(size_t)ly * n + q] != 0;
             const double* m = M + 8 * q;
             const cd a(m[0], m[1]), b(m[2], m[3]), c(m[4], m[5]), d(m[6], m[7]);
             double* o = gl.m.data() + ((size_t)ly * n + q) * 8;
@@ -900,19 +894,29 @@ int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& prog, co
     if (nblk > 0) {
         if (fx) return fail(SV_ERR_UNSUPPORTED, "general layers need allocated scratch");
         if (!prog.layers || prog.nq != s->n) return fail(SV_ERR_ARG, "internal: general layers without matrices");
+        // qubits a general op of a pass acts on: the active tile bits of its group
+        auto op_qubits = [&](const Geometry& geo) {
+            std::vector<int> qs;
+            for (int l = geo.g == 0 ? 0 : geo.c; l < std::min(geo.T, geo.n); l++) {
+                const int q = global_bit(geo, l);
+                if (q >= 0) qs.push_back(q);
+            }
+            return qs;
+        };
         int nl = 0;
-        std::vector<std::vector<int>> pass_layers;
+        std::vector<std::vector<std::pair<int, std::vector<int>>>> pass_ops;
         for (const Pass& ps : prog.passes) {
-            std::vector<int> pl;
+            const std::vector<int> qs = op_qubits(plan.by_nv[ps.nv][ps.group]);
+            std::vector<std::pair<int, std::vector<int>>> ops;
             for (const Op& op : ps.ops)
                 if (op.kind == OP_MIX && (op.flags & MIX_GEN)) {
                     nl = std::max(nl, op.qidx + 1);
-                    pl.push_back(op.qidx);
+                    ops.emplace_back(op.qidx, qs);
                 }
-            if (!pl.empty()) pass_layers.push_back(pl);
+            if (!ops.empty()) pass_ops.push_back(ops);
         }
         const GenLayers gl = unit_diagonal_layers(prog.layers, nl, s->n, knob_for("genunit", (int)s->dt, s->n) != 0,
-                                                  pass_layers);
+                                                  pass_ops);
         const size_t need = nblk * (size_t)kGenBlock;
         // the staging buffer may still feed the previous call's copy
         HIPCHECK(hipStreamSynchronize(s->stream));
@@ -945,14 +949,11 @@ int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& prog, co
                     for (int c = 1; c < 8; c += 2) real = real && blk[8 * l + c] == 0.0;
                 }
                 genreal[pi][i] = real;
-                if (gl.unit[layer]) {
-                    // the moduli of the op's qubits (its active tile bits) join the pending scale
+                const std::vector<int> qs = op_qubits(geo);
+                if (!qs.empty() && gl.unit[(size_t)layer * s->n + qs[0]]) {  // all or none of the op's qubits
+                    // the moduli of the op's qubits join the pending scale
                     double sc = 1.0;
-                    const int l0 = geo.g == 0 ? 0 : geo.c;
-                    for (int l = l0; l < std::min(geo.T, geo.n); l++) {
-                        const int q = global_bit(geo, l);
-                        if (q >= 0) sc *= gl.mod[(size_t)layer * s->n + q];
-                    }
+                    for (int q : qs) sc *= gl.mod[(size_t)layer * s->n + q];
                     op.flags |= MIX_GUNIT;
                     op.b = sc;
                 }
