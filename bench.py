@@ -44,7 +44,7 @@ def main():
     ap.add_argument("--dtype", default="c128")
     ap.add_argument("--no-extras", action="store_true", help="skip gradient / c64 / CPU-baseline legs")
     ap.add_argument("--extras", default="all",
-                    help="comma list of extra legs: grad,c64,exact_cover,hadamard,qsds,batch_scan,optimizer,full,cpu "
+                    help="comma list of extra legs: grad,grad_p8,c64,exact_cover,hadamard,qsds,batch_scan,optimizer,full,cpu "
                          "(default all)")
     ap.add_argument("--cpu-sample-n", type=int, default=28)
     ap.add_argument("--cpu-sample-p", type=int, default=4)
@@ -162,7 +162,7 @@ def main():
 
     extras = {}
     legs = set() if args.no_extras else (
-        {"grad", "c64", "exact_cover", "hadamard", "qsds", "batch_scan", "optimizer", "full", "cpu"}
+        {"grad", "grad_p8", "c64", "exact_cover", "hadamard", "qsds", "batch_scan", "optimizer", "full", "cpu"}
         if args.extras == "all"
         else set(args.extras.split(",")))
     if "grad" in legs:
@@ -182,6 +182,49 @@ def main():
                           "max_abs_grad": float(max(np.max(np.abs(dg)), np.max(np.abs(db))))}
         log(f"[bench] grad {t_grad:.2f} ms vs FD {t_fd:.2f} ms")
         del lam
+    if "grad_p8" in legs:
+        # depth p = 8 (16 parameters) at n = 30 in complex64: forward <H_C> and the adjoint
+        # gradient against 2p + 1 = 17 forward evaluations; the complex64 gradient's error
+        # against the complex128 adjoint of the same instance, relative to max|g|
+        n8, p8 = 30, 8
+        H8 = sv.Ising.from_instance(I.degree4_int2(n8, 4 + n8))
+        sv.ground(H8)
+        g8, b8 = I.uniform_params(p8, 9, -0.9, 0.9)
+        s8 = sv.State(n8, "c64")
+        l8 = sv.State(n8, "c64")
+
+        def med(fn, reps=5):
+            fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                ts.append((time.perf_counter() - t0) * 1e3)
+            return sorted(ts)[reps // 2]
+
+        t_f8 = med(lambda: sv.qaoa_energy(s8, H8, g8, b8))
+        t_g8 = med(lambda: sv.grad(s8, l8, H8, g8, b8))
+        _, dg8, db8 = sv.grad(s8, l8, H8, g8, b8)
+        s8.close()
+        l8.close()
+        torch.cuda.empty_cache()
+        r8, q8 = sv.State(n8, "c128"), sv.State(n8, "c128")
+        _, rg8, rb8 = sv.grad(r8, q8, H8, g8, b8)
+        r8.close()
+        q8.close()
+        ref8 = np.concatenate([rg8, rb8])
+        err8 = float(np.max(np.abs(np.concatenate([dg8, db8]) - ref8)) / np.max(np.abs(ref8)))
+        extras["grad_p8"] = {"workload": "QAOA p=8 (16 parameters), n=30 complex64, degree-4 Ising J in [-2,2]",
+                             "forward_ms": round(t_f8, 3), "grad_ms": round(t_g8, 3),
+                             "fd_forward_diff_ms": round((2 * p8 + 1) * t_f8, 3),
+                             "speedup_vs_fd": round((2 * p8 + 1) * t_f8 / t_g8, 3),
+                             "target": round((2 * p8 + 1) / 3, 3), "c64_grad_err_vs_c128_rel_max": err8}
+        log(f"[bench] p=8 n=30 c64: forward {t_f8:.2f} ms, grad {t_g8:.2f} ms "
+            f"({(2 * p8 + 1) * t_f8 / t_g8:.2f}x vs 17 forwards), c64 error {err8:.2e} of max|g|")
+        del H8
+        torch.cuda.empty_cache()
     if "c64" in legs:
         # complex64 storage, same instance
         s64 = sv.State(n, "c64")
