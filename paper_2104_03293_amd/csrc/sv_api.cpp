@@ -884,8 +884,13 @@ extern "C" int sv_stream_ceiling(sv_state s, int c, int lo, double* ms) {
     a.c = c;
     a.lo = g > 0 ? lo : T;
     a.g = g;
-    a.xcd = knob_for("xcd", (int)s->dt, s->n);
-    if (a.xcd < 0) a.xcd = ((size_t(1) << s->n) * elem_size(s->dt)) > (size_t(64) << 30) ? 3 : 1;
+    {
+        Geometry geo{};
+        geo.c = c;
+        geo.lo = a.lo;
+        geo.g = g;
+        a.xcd = xcd_order(knob_for("xcd", (int)s->dt, s->n), geo, s->n, s->dt);
+    }
     hipEvent_t e0, e1;
     HIPCHECK(hipEventCreate(&e0));
     hipError_t e = hipEventCreate(&e1);

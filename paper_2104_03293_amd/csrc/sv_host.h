@@ -175,4 +175,5 @@ int fetch_results(sv_state_s* s, int nres);
 // last state is freed, so they live no longer than the states that use them.
 void release_plain_geos();
 double ground_tol(const sv_ising_s* H);
+int xcd_order(int x, const Geometry& geo, int n, sv_dtype dt);  // PassArgs::xcd for knob value x
 int run_ground(sv_ising_s* H, hipStream_t stream);

@@ -64,7 +64,8 @@ std::map<std::string, int> g_knobs = {
     {"split", 0},     // bits above the contiguous tile: 0 = near-equal groups, 1 = largest groups first
     {"xcd", -1},      // x > 0: XCD-aware tile order, 8 * 2^(x-1) interleaved streams of contiguous tiles;
                       // 0: tile = workgroup index; -1: 8 streams for states up to 64 GiB, 32 above
-                      // (n = 32 complex128: 241 -> 226 ms per p = 4 evaluation; n = 33: 589 -> 461 ms)
+                      // (n = 32 complex128: 241 -> 226 ms per p = 4 evaluation; n = 33: 589 -> 461 ms);
+                      // -2: per tile group, 32 streams for groups from bit 20 up (and above 64 GiB)
     {"adjzeta", -1},  // adjoint: 1 = two one-vector reverse sweeps of psi +- i t lambda; 0 = one sweep of
                       // both vectors (two-vector passes); -1 = 1 for complex128 (n = 32, p = 4: 731 vs
                       // 767 ms), 0 for complex64 (449 vs 432 ms, and the f32 rounding of the two
@@ -78,7 +79,7 @@ const std::map<std::string, std::pair<int, int>> g_knob_range = {
     {"fuse", {0, 1}},    {"cmin64", {0, 8}},   {"cmin128", {0, 8}},  {"ntmin", {0, 64}},   {"persist", {0, 8}},
     {"stagger", {0, 64}}, {"snake", {0, 2}},   {"dpp", {0, 1}},      {"ldsswz", {3, 5}},   {"batchwide", {0, 2}},
     {"batch128", {0, 1}}, {"c64t13", {0, 1}},  {"c64occ", {0, 1}},   {"c64g4", {0, 1}},    {"kc34", {0, 1}},
-    {"c64g14", {0, 2}},  {"ntinit", {0, 1}},   {"batchslab", {0, 4096}}, {"genunit", {0, 1}},   {"split", {0, 1}},    {"xcd", {-1, 5}},      {"c128t14", {0, 1}}, {"adjzeta", {-1, 1}},
+    {"c64g14", {0, 2}},  {"ntinit", {0, 1}},   {"batchslab", {0, 4096}}, {"genunit", {0, 1}},   {"split", {0, 1}},    {"xcd", {-2, 5}},      {"c128t14", {0, 1}}, {"adjzeta", {-1, 1}},
     {"fail_next_launch", {0, 1}},
 };
 }  // namespace

@@ -418,6 +418,17 @@ void release_plain_geos() {
     g_plain_geos.clear();
 }
 
+// Tile order of a pass (PassArgs::xcd) for knob value x: x >= 0 as given; -1: 8
+// interleaved streams (x = 1) up to 64 GiB states, 32 (x = 3) above; -2: by tile
+// group, 32 streams for a group whose bits start at 20 or above (runs megabytes
+// apart) and for every group of a state above 64 GiB, 8 for the others.
+int xcd_order(int x, const Geometry& geo, int n, sv_dtype dt) {
+    const bool big = ((size_t(1) << n) * elem_size(dt)) > (size_t(64) << 30);
+    if (x == -1) return big ? 3 : 1;
+    if (x == -2) return (big || (geo.g > 0 && geo.lo >= 20)) ? 3 : 1;
+    return x;
+}
+
 // lookup_only: return the cached table or fail (calls that may not allocate).
 static int get_geobuf(const Geometry& geo, sv_ising_s* H, sv_dtype dt, GeoBuf** out, bool lookup_only = false) {
     uint64_t sig = 1469598103934665603ull;  // FNV-1a over the layout description
@@ -1001,8 +1012,7 @@ int run_program(sv_state_s* s, sv_state_s* lam, sv_ising_s* H, Program& prog, co
         a.swz = lds_swz_bits(s->dt, s->n);
         a.grid = persist * ncu;
         a.stagger = stagger;
-        a.xcd = knob_for("xcd", (int)s->dt, s->n);
-        if (a.xcd < 0) a.xcd = ((size_t(1) << s->n) * elem_size(s->dt)) > (size_t(64) << 30) ? 3 : 1;
+        a.xcd = xcd_order(knob_for("xcd", (int)s->dt, s->n), geo, s->n, s->dt);
         for (const Op& op : p.ops) {
             a.nops += op.kind != 0;
             if (op.kind == OP_POINT && H) a.need_e = 1;

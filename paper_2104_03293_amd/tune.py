@@ -35,7 +35,7 @@ import time
 from pathlib import Path
 
 FORWARD = {
-    "xcd": [-1, 0, 1, 2, 3, 4],
+    "xcd": [-1, -2, 0, 1, 2, 3, 4],
     "snake": [1, 0, 2],
     "ntmin": [4, 3, 5, 6],
     "ldsswz": [4, 3, 5],

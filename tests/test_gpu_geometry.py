@@ -337,13 +337,13 @@ def test_xcd_tile_orders_agree(sv, orc, record_error, dtype, n):
     """The XCD-aware tile orders only change which workgroup takes which tile;
     the per-tile partial sums are indexed by tile, so the state, the observables
     and the adjoint gradient are bit-identical for every order (knob xcd = 0 ..
-    5, and the automatic choice -1; at n = 15 the tile count is below the
+    5, and the automatic choices -1 and -2; at n = 15 the tile count is below the
     stream count and the plain order is kept), and they match the oracle."""
     inst = I.degree4_int2(n, 640 + n)
     H = sv.Ising.from_instance(inst)
     g, b = I.uniform_params(3, 641 + n, -1.1, 1.1)
     out = {}
-    for x in (-1, 0, 1, 2, 3, 4, 5):
+    for x in (-2, -1, 0, 1, 2, 3, 4, 5):
         with Knob(sv, "xcd", x):
             s = sv.State(n, dtype)
             lam = sv.State(n, dtype)
