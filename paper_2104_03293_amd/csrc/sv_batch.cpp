@@ -92,7 +92,7 @@ extern "C" int sv_batch_p1_scan(int n_inst, const sv_ising* insts, int n_gamma, 
     size_t part_doubles = 0;
     if (sliced)
         for (int n = S + 1; n <= max_n; n++)
-            part_doubles = std::max(part_doubles, (size_t)states_per_launch(n) * 2 << (n - S));
+            part_doubles = std::max(part_doubles, (size_t)states_per_launch(n) * 2 << (n - batch_slice_bits((int)dtype, n)));
     const size_t nout = (size_t)n_inst * n_gamma * n_beta;
     hipStream_t st = (hipStream_t)stream;
     // device buffers
@@ -195,6 +195,7 @@ extern "C" int sv_batch_p1_scan(int n_inst, const sv_ising* insts, int n_gamma, 
             int nlaunch = 0;
             auto finish_of = [&](BatchArgs& bs) {
                 bs.f_n = prev.s_n;
+                bs.f_nh = prev.s_count > 0 ? prev.s_n - batch_slice_bits((int)dtype, prev.s_n) : 0;
                 bs.f_u0 = prev.s_u0;
                 bs.f_base = prev.s_base;
                 bs.f_count = prev.s_count;

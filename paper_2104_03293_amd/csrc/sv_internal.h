@@ -274,6 +274,7 @@ struct BatchArgs {
     // the previous launch, whose states the slice kernel of this one finishes
     // (f_count = 0: none)
     int32_t f_n, f_u0, f_count;
+    int32_t f_nh;           // partial sums per state of the previous launch: 2^f_nh
     int64_t f_base;
     const double* f_part;
 };
@@ -287,6 +288,7 @@ int launch_batch_sliced(int dtype, const BatchArgs& a, int wide, void* stream);
 int launch_batch_finish(const BatchArgs& a, void* stream);
 int batch_lds_bits(int dtype, int wide);  // log2 of the LDS-resident state of a batch variant
 int batch_lut_cap(int dtype, int wide);   // phase-table entries of a batch variant
+int batch_slice_bits(int dtype, int n);   // log2 of the slice of an n-qubit state on the sliced path
 
 // ---------------------------------------------------------------- fixed scratch
 // Device region that a call which may not allocate uses instead of the state's

@@ -1981,10 +1981,9 @@ __device__ __forceinline__ double batch_reduce_beta(double beta, int n, uint32_t
 }
 
 // <H_C> and P_gs of state s of a launch (qubits n, first unit u0, first group
-// state base): its 2^(n - S) partial sums in a fixed order, times cos(beta)^{2n}.
-__device__ void batch_finish_state(const BatchArgs& a, int S, int n, int u0, int64_t base, const double* part,
+// state base): its 2^nh partial sums in a fixed order, times cos(beta)^{2n}.
+__device__ void batch_finish_state(const BatchArgs& a, int nh, int n, int u0, int64_t base, const double* part,
                                    int s) {
-    const int nh = n - S;
     const int64_t g = base + s;
     const int u = u0 + (int)(g / a.nb);
     const int b = (int)(g % a.nb);
@@ -2002,14 +2001,18 @@ __device__ void batch_finish_state(const BatchArgs& a, int S, int n, int u0, int
     a.out_p[o] = sp * sc;
 }
 
-template <typename Real, int NTH, int S, int LUTN, int MINW>
+// B: bits of a register block (5: 2^13 slices in rounds of 5, 5 and 3 bits; 4: 2^12
+// slices in three rounds of 4 bits)
+template <typename Real, int NTH, int S, int LUTN, int MINW, int B = 5>
 __global__ void __launch_bounds__(NTH, MINW) k_batch_slices(const BatchArgs a) {
     using V2 = typename V2T<Real>::type;
     constexpr int G = BatchCfg<Real>::G;
     constexpr int U = kBatchUnroll;
-    constexpr int LB = S - 5;
-    constexpr int MB = S - 10;
-    static_assert(S >= 10 && S <= 15, "slice rounds assume 10 <= S <= 15");
+    constexpr int NB = 1 << B;
+    constexpr int LB = S - B;
+    constexpr int MB = S - 2 * B;
+    static_assert(MB >= 1 && MB <= B, "slice rounds assume B < S - B <= 2 B");
+    static_assert((1 << S) % (NTH * kBatchUnroll) == 0, "phase loop assumes whole blocks");
     __shared__ V2 st[1 << S];
     __shared__ V2 lut[LUTN];  // 2^{-n/2} exp(-i gamma E), rounded once to the storage type
     const int t = threadIdx.x;
@@ -2018,7 +2021,7 @@ __global__ void __launch_bounds__(NTH, MINW) k_batch_slices(const BatchArgs a) {
     const uint32_t nsl = (uint32_t)a.s_count << nh;
     if (blockIdx.x >= nsl) {  // trailing workgroups: the previous launch's states
         const int fs = (int)(blockIdx.x - nsl) * NTH + t;
-        if (fs < a.f_count) batch_finish_state(a, S, a.f_n, a.f_u0, a.f_base, a.f_part, fs);
+        if (fs < a.f_count) batch_finish_state(a, a.f_nh, a.f_n, a.f_u0, a.f_base, a.f_part, fs);
         return;
     }
     const uint32_t s = blockIdx.x >> nh;
@@ -2059,47 +2062,47 @@ __global__ void __launch_bounds__(NTH, MINW) k_batch_slices(const BatchArgs a) {
         }
     }
     __syncthreads();
-    // bits S-5..S-1 in registers as the phases are formed
+    // bits S-B..S-1 in registers as the phases are formed
     const uint16_t* Xs = a.eidx + off;
     for (uint32_t l = t; l < (1u << LB); l += NTH) {
         const uint32_t bl = opaque(bswz(l, G));
-        V2 v[32];
+        V2 v[NB];
         if (intE) {
-            uint16_t x[32];
+            uint16_t x[NB];
 #pragma unroll
-            for (int r = 0; r < 32; r++) x[r] = Xs[l | ((uint32_t)r << LB)];
+            for (int r = 0; r < NB; r++) x[r] = Xs[l | ((uint32_t)r << LB)];
 #pragma unroll
-            for (int r = 0; r < 32; r++) v[r] = lut[x[r]];
+            for (int r = 0; r < NB; r++) v[r] = lut[x[r]];
         } else {
 #pragma unroll
-            for (int r = 0; r < 32; r++) v[r] = st[bl ^ bswz((uint32_t)r << LB, G)];
+            for (int r = 0; r < NB; r++) v[r] = st[bl ^ bswz((uint32_t)r << LB, G)];
         }
-        reg_mix<Real, 5>(v, tq);
+        reg_mix<Real, B>(v, tq);
 #pragma unroll
-        for (int r = 0; r < 32; r++) st[bl ^ bswz((uint32_t)r << LB, G)] = v[r];
+        for (int r = 0; r < NB; r++) st[bl ^ bswz((uint32_t)r << LB, G)] = v[r];
     }
     __syncthreads();
-    // bits 0..4
+    // bits 0..B-1
     for (uint32_t q = t; q < (1u << LB); q += NTH) {
-        const uint32_t bq = opaque(bswz(q << 5, G));
-        V2 v[32];
+        const uint32_t bq = opaque(bswz(q << B, G));
+        V2 v[NB];
 #pragma unroll
-        for (int r = 0; r < 32; r++) v[r] = st[bq ^ bswz((uint32_t)r, G)];
-        reg_mix<Real, 5>(v, tq);
+        for (int r = 0; r < NB; r++) v[r] = st[bq ^ bswz((uint32_t)r, G)];
+        reg_mix<Real, B>(v, tq);
 #pragma unroll
-        for (int r = 0; r < 32; r++) st[bq ^ bswz((uint32_t)r, G)] = v[r];
+        for (int r = 0; r < NB; r++) st[bq ^ bswz((uint32_t)r, G)] = v[r];
     }
     __syncthreads();
-    // bits 5..S-6 on the way from LDS to the slab
+    // bits B..S-B-1 on the way from LDS to the slab
     for (uint32_t gq = t; gq < (1u << (S - MB)); gq += NTH) {
-        const uint32_t zb = (gq & 31u) | ((gq >> 5) << (5 + MB));
+        const uint32_t zb = (gq & (NB - 1u)) | ((gq >> B) << (B + MB));
         const uint32_t bz = opaque(bswz(zb, G));
         V2 v[1 << MB];
 #pragma unroll
-        for (int r = 0; r < (1 << MB); r++) v[r] = st[bz ^ bswz((uint32_t)r << 5, G)];
+        for (int r = 0; r < (1 << MB); r++) v[r] = st[bz ^ bswz((uint32_t)r << B, G)];
         reg_mix<Real, MB>(v, tq);
 #pragma unroll
-        for (int r = 0; r < (1 << MB); r++) Ss[zb | ((uint32_t)r << 5)] = v[r];
+        for (int r = 0; r < (1 << MB); r++) Ss[zb | ((uint32_t)r << B)] = v[r];
     }
 }
 
@@ -2180,44 +2183,135 @@ __global__ void __launch_bounds__(NTH) k_batch_columns(const BatchArgs a) {
     }
 }
 
-template <typename Real>
+// Six high bits (64 values per column): each column is held by a lane pair, 32
+// values per lane; row bits 0-4 in registers, row bit 5 across the pair (both
+// members take x <- x - i t x_partner).
+template <typename Real, int S>
+__global__ void __launch_bounds__(128) k_batch_columns_pair(const BatchArgs a) {
+    using V2 = typename V2T<Real>::type;
+    constexpr int U = kBatchUnroll;
+    constexpr int NH = 6;
+    constexpr int NTH = 128;
+    static_assert(S - NH == 6, "a block of 64 columns per 128 threads");
+    __shared__ double red[NTH / 64][2];
+    const int t = threadIdx.x;
+    const int n = S + NH;
+    const uint32_t s = blockIdx.x >> NH;
+    const uint32_t cb = blockIdx.x & ((1u << NH) - 1u);
+    const int64_t g = a.s_base + s;
+    const int u = a.s_u0 + (int)(g / a.nb);
+    const int b = (int)(g % a.nb);
+    const BatchInst in = a.inst[a.unit_inst[u]];
+    const bool intE = in.lut_n > 0;
+    const int xmin = intE ? (int)in.emin - in.lut_lo : 0;  // table index of the ground energy
+    uint32_t fl;
+    const Real tq = (Real)tan(batch_reduce_beta(a.betas[b], n, fl));
+    const V2* __restrict__ Sv = reinterpret_cast<const V2*>(a.slab) + ((uint64_t)s << n);
+    const uint16_t* X = a.eidx + in.eoff;
+    const double* E = a.etab + in.eoff;
+    const uint32_t h = (uint32_t)t & 1u;  // upper or lower 32 rows
+    const uint32_t l = opaque((cb << (S - NH)) + ((uint32_t)t >> 1));
+    const uint32_t r0 = h << 5;
+    V2 v[32];
+#pragma unroll
+    for (int j = 0; j < 32; j++) v[j] = Sv[((r0 + (uint32_t)j) << S) | l];
+    reg_mix<Real, 5>(v, tq);
+#pragma unroll
+    for (int j = 0; j < 32; j++) {
+        const Real pr = __shfl_xor(v[j].x, 1), pi = __shfl_xor(v[j].y, 1);
+        v[j].x = fma(tq, pi, v[j].x);
+        v[j].y = fma(-tq, pr, v[j].y);
+    }
+    double r_e = 0.0, r_p = 0.0;
+    if (intE) {
+#pragma unroll
+        for (int j0 = 0; j0 < 32; j0 += U) {
+            uint16_t x[U];
+#pragma unroll
+            for (int j = 0; j < U; j++) x[j] = X[(((r0 + (uint32_t)(j0 + j)) << S) | l) ^ fl];
+#pragma unroll
+            for (int j = 0; j < U; j++) {
+                const V2 w = v[j0 + j];
+                const double p2 = (double)w.x * w.x + (double)w.y * w.y;
+                r_e += (double)(in.lut_lo + (int)x[j]) * p2;
+                if ((int)x[j] == xmin) r_p += p2;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < 32; j++) {
+            const double p2 = (double)v[j].x * v[j].x + (double)v[j].y * v[j].y;
+            const double e = E[(((r0 + (uint32_t)j) << S) | l) ^ fl];
+            r_e += e * p2;
+            if (fabs(e - in.emin) <= in.etol) r_p += p2;
+        }
+    }
+    // fixed-order workgroup sum
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        r_e += __shfl_xor(r_e, o);
+        r_p += __shfl_xor(r_p, o);
+    }
+    if ((t & 63) == 0) {
+        red[t >> 6][0] = r_e;
+        red[t >> 6][1] = r_p;
+    }
+    __syncthreads();
+    if (t == 0) {
+        a.part[2 * (uint64_t)blockIdx.x] = red[0][0] + red[1][0];
+        a.part[2 * (uint64_t)blockIdx.x + 1] = red[0][1] + red[1][1];
+    }
+}
+
+template <typename Real, int S>
 static int launch_batch_columns(const BatchArgs& a, unsigned grid, hipStream_t st) {
-    switch (a.s_n - 13) {
-        case 1: hipLaunchKernelGGL((k_batch_columns<Real, 256, 13, 1>), dim3(grid), dim3(256), 0, st, a); break;
-        case 2: hipLaunchKernelGGL((k_batch_columns<Real, 256, 13, 2>), dim3(grid), dim3(256), 0, st, a); break;
-        case 3: hipLaunchKernelGGL((k_batch_columns<Real, 256, 13, 3>), dim3(grid), dim3(256), 0, st, a); break;
-        case 4: hipLaunchKernelGGL((k_batch_columns<Real, 256, 13, 4>), dim3(grid), dim3(256), 0, st, a); break;
-        case 5: hipLaunchKernelGGL((k_batch_columns<Real, 256, 13, 5>), dim3(grid), dim3(256), 0, st, a); break;
+    switch (a.s_n - S) {
+        case 1: hipLaunchKernelGGL((k_batch_columns<Real, 256, S, 1>), dim3(grid), dim3(256), 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_batch_columns<Real, 256, S, 2>), dim3(grid), dim3(256), 0, st, a); break;
+        case 3: hipLaunchKernelGGL((k_batch_columns<Real, 256, S, 3>), dim3(grid), dim3(256), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_batch_columns<Real, 256, S, 4>), dim3(grid), dim3(256), 0, st, a); break;
+        case 5: hipLaunchKernelGGL((k_batch_columns<Real, 256, S, 5>), dim3(grid), dim3(256), 0, st, a); break;
+        case 6:
+            if constexpr (S == 12) {
+                hipLaunchKernelGGL((k_batch_columns_pair<Real, S>), dim3(grid), dim3(128), 0, st, a);
+                break;
+            }
+            return (int)hipErrorInvalidValue;
         default: return (int)hipErrorInvalidValue;
     }
     return (int)hipGetLastError();
 }
 
-__global__ void __launch_bounds__(256) k_batch_finish(const BatchArgs a, int S) {
+__global__ void __launch_bounds__(256) k_batch_finish(const BatchArgs a) {
     const int s = blockIdx.x * 256 + threadIdx.x;
-    if (s < a.f_count) batch_finish_state(a, S, a.f_n, a.f_u0, a.f_base, a.f_part, s);
+    if (s < a.f_count) batch_finish_state(a, a.f_nh, a.f_n, a.f_u0, a.f_base, a.f_part, s);
 }
+
+// Slice bits of the sliced path: complex128 states in 2^12-amplitude slices (72 KiB of
+// LDS, two workgroups per CU; the column kernels then hold 2 to 6 high bits), complex64
+// ones in 2^13 slices.
+int batch_slice_bits(int dtype, int) { return dtype == 2 ? 12 : 13; }
 
 int launch_batch_sliced(int dtype, const BatchArgs& a, int wide, void* stream) {
     hipStream_t st = (hipStream_t)stream;
-    const int S = batch_lds_bits(dtype, wide);
-    if (S != 13 || a.s_n <= S || a.s_n > S + 5 || a.s_count < 1) return (int)hipErrorInvalidValue;
+    const int S = batch_slice_bits(dtype, a.s_n);
+    if (batch_lds_bits(dtype, wide) != 13 || a.s_n <= 13 || a.s_n > S + (S == 12 ? 6 : 5) || a.s_count < 1)
+        return (int)hipErrorInvalidValue;
     const unsigned grid = (unsigned)a.s_count << (a.s_n - S);
-    const int nth = dtype == 2 ? 512 : 256;
-    const unsigned fin = a.f_count > 0 ? (unsigned)((a.f_count + nth - 1) / nth) : 0u;
+    const unsigned fin = a.f_count > 0 ? (unsigned)((a.f_count + 255) / 256) : 0u;  // 256-thread workgroups
     if (dtype == 2)
-        hipLaunchKernelGGL((k_batch_slices<double, 512, 13, 1024, 1>), dim3(grid + fin), dim3(512), 0, st, a);
+        hipLaunchKernelGGL((k_batch_slices<double, 256, 12, 512, 2, 4>), dim3(grid + fin), dim3(256), 0, st, a);
     else
         hipLaunchKernelGGL((k_batch_slices<float, 256, 13, 1024, 2>), dim3(grid + fin), dim3(256), 0, st, a);
     int e = (int)hipGetLastError();
     if (e) return e;
-    return dtype == 2 ? launch_batch_columns<double>(a, grid, st) : launch_batch_columns<float>(a, grid, st);
+    return dtype == 2 ? launch_batch_columns<double, 12>(a, grid, st) : launch_batch_columns<float, 13>(a, grid, st);
 }
 
 int launch_batch_finish(const BatchArgs& a, void* stream) {
     if (a.f_count < 1) return 0;
     hipLaunchKernelGGL(k_batch_finish, dim3((unsigned)((a.f_count + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
-                       a, 13);
+                       a);
     return (int)hipGetLastError();
 }
 
@@ -2226,7 +2320,7 @@ int launch_batch_finish(const BatchArgs& a, void* stream) {
 // waves (wide = 1) or four (wide = 0), one workgroup per CU; complex64 2^13 states with four
 // waves (wide = 2), two workgroups per CU.  Phase tables hold 1024 entries.
 int batch_lds_bits(int dtype, int wide) { return dtype == 2 ? 13 : (wide == 2 ? 13 : 14); }
-int batch_lut_cap(int, int) { return 1024; }
+int batch_lut_cap(int dtype, int) { return dtype == 2 ? 512 : 1024; }  // complex128: the 2^12-slice kernel's table
 
 int launch_batch_scan(int dtype, const BatchArgs& a, int grid, int wide, void* stream) {
     if (a.scratch_elems == 0 && ((dtype == 2 && wide == 1) || (dtype != 2 && wide == 2))) {  // LDS-resident units only
